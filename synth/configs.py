@@ -1,0 +1,82 @@
+"""The five evaluation workloads (shapes, distributions, operator sets).
+
+Each workload stands in for a dataset class of the paper (Tab. 1 sizes span
+60 to 100,000 rows and 7 to 12 features; Tab. 2 templates have depth 4, 6 or 8).
+Real data is not available, so X is drawn from a stated distribution and y is a
+closed-form target of it.
+"""
+from dataclasses import dataclass, field
+from typing import Callable, Tuple
+
+import numpy as np
+
+from . import symbols as S
+
+
+def _t_cfg1(x):
+    return x[0] * x[1] + x[0] / (1.0 + x[1] ** 2)
+
+
+def _t_cfg2(x):
+    return 1.5 * x[0] * x[3] - np.sin(x[2]) / (1.0 + x[5] ** 2)
+
+
+def _t_cfg4(x):
+    return 2.3 * x[0] ** 2 - 0.7 * x[1] * x[4] + np.cos(1.9 * x[2])
+
+
+def _t_cfg5(x):
+    return x[0] * x[1] * x[2] / (x[3] * (x[4] - x[5]) ** 2) * (1.0 + np.cos(x[6] * x[7] / x[8]))
+
+
+@dataclass(frozen=True)
+class Config:
+    cid: int
+    name: str
+    M: int
+    heights: Tuple[int, ...]      # one height, or the set sampled uniformly
+    funcs: Tuple[int, ...]
+    F: int
+    N: int
+    x_dist: str                   # "U(lo,hi)" or "N(0,1)"
+    x_lo: float
+    x_hi: float
+    target: Callable = field(repr=False)
+    noise: float = 0.0            # std of additive N(0,1) noise on y
+    erc_lo: float = -1.0
+    erc_hi: float = 1.0
+    variant_frac: float = 0.0     # share of GOM-style offspring in the batch
+    description: str = ""
+
+    @property
+    def h_max(self) -> int:
+        return max(self.heights)
+
+    @property
+    def L_max(self) -> int:
+        return 2 ** (self.h_max + 1) - 1
+
+    @property
+    def C_max(self) -> int:
+        return 2 ** self.h_max
+
+
+CONFIGS = {
+    1: Config(1, "cfg1-tiny", 64, (3,), S.FUNCS_BASIC, 2, 1_000, "U", -1.0, 1.0, _t_cfg1,
+              description="64 x h3 (15 nodes), {+,-,*,/p}, F=2 U(-1,1), N=1e3"),
+    2: Config(2, "cfg2-plain-at-scale", 1024, (4,), S.FUNCS_8, 10, 100_000, "N", 0.0, 1.0, _t_cfg2,
+              noise=0.01,
+              description="1024 x h4 (31 nodes), 8 ops, F=10 N(0,1), N=1e5"),
+    3: Config(3, "cfg3-gom-batch", 4096, (3, 4, 5, 6), S.FUNCS_8, 10, 1_000_000, "U", -3.0, 3.0, _t_cfg1,
+              variant_frac=0.3,
+              description="4096 x h3..6 (15..127 nodes), 8 ops, F=10 U(-3,3), N=1e6, 30% GOM offspring"),
+    4: Config(4, "cfg4-differentiation", 2048, (5,), S.FUNCS_8, 5, 500_000, "U", -1.0, 1.0, _t_cfg4,
+              erc_lo=-2.0, erc_hi=2.0,
+              description="2048 x h5 (63 nodes, <=32 ERCs U(-2,2)), 8 ops, F=5 U(-1,1), N=5e5"),
+    5: Config(5, "cfg5-large-template", 8192, (7,), S.FUNCS_ALL, 9, 10_000_000, "U", 1.0, 5.0, _t_cfg5,
+              description="8192 x h7 (255 nodes), 11 ops, F=9 U(1,5), N=1e7"),
+}
+
+
+def get_config(cid: int) -> Config:
+    return CONFIGS[int(cid)]
