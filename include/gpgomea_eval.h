@@ -1,0 +1,177 @@
+/*
+ * gpgomea_eval.h -- C ABI of the MI355X (gfx950) batched fitness evaluator for
+ * GP-GOMEA template individuals.
+ *
+ * What is computed (the data-parallel hot path of GPU GP-GOMEA):
+ *   Every individual is a postfix (Reverse Polish) program over the active
+ *   nodes of a fixed-size tree template (Section 3.2, "Data Structure of
+ *   Individuals", Fig. 1).  It is evaluated on every row of a dataset with a
+ *   stack interpreter (Section 3.2, "Evaluation on the GPU"), and its squared
+ *   errors are reduced to one fitness value per individual: the MSE of Eq. 1,
+ *   or the MSE after the least-squares affine fit y ~ a + b*p (linear scaling;
+ *   App. A.2 notes the paper's GPU path lacks it), with NMSE = fitness/Var(y)
+ *   (Eq. 2, population variance).  gpgomea_grad_consts adds the gradient of
+ *   that fitness with respect to every constant of every individual
+ *   (reverse mode; not in the paper).  The batch is the set of changed
+ *   offspring that Alg. 1 collects before its single Evaluate call.
+ *
+ * Conventions common to all entry points
+ *   - Every pointer named "device" is GPU memory owned by the caller.  The
+ *     library never allocates device memory and never reads device data on
+ *     the host.  Scratch space is the caller's `workspace` buffer, of at least
+ *     gpgomea_workspace_bytes(...) bytes, 256-byte aligned.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  GPU entry points
+ *     only enqueue work and return; outputs are valid after the stream has
+ *     reached that point.  Inputs and the workspace must stay alive and
+ *     unmodified until then.  Two calls that share a workspace must not run
+ *     concurrently.
+ *   - Return value: GPGOMEA_OK (0) or a negative GPGOMEA_E_* code; the message
+ *     of the last failure on the calling thread is gpgomea_last_error().
+ *     Argument and shape errors are detected on the host before anything is
+ *     enqueued.  Per-individual problems never fail a call: they go to
+ *     status[i] (1 = a prediction was NaN or infinite, fitness = +inf;
+ *     2 = malformed program, fitness = +inf).
+ *
+ * Program encoding (one signed byte per postfix token, see gpgomea_ops.h):
+ *   0 + | 1 - | 2 * | 3 protected / | 4 sin | 5 cos | 6 square | 7 sqrt|a|
+ *   8 exp(clamp(a,-80,80)) | 9 protected log|a| | 10 protected pow
+ *   32 constant (takes the next value of the individual's constant list)
+ *   64+k variable k | -1 end / padding.
+ *   Binary operators take the earlier-pushed operand as the left one.
+ */
+#ifndef GPGOMEA_EVAL_H
+#define GPGOMEA_EVAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GPGOMEA_OK 0
+#define GPGOMEA_E_ARG (-1)         /* NULL pointer or invalid flag            */
+#define GPGOMEA_E_SHAPE (-2)       /* a size is out of the supported range    */
+#define GPGOMEA_E_PROGRAM (-3)     /* host codec: malformed program/genotype  */
+#define GPGOMEA_E_HIP (-4)         /* a HIP runtime call failed               */
+#define GPGOMEA_E_WORKSPACE (-5)   /* workspace too small or misaligned       */
+#define GPGOMEA_E_UNSUPPORTED (-6) /* combination not implemented             */
+
+/* ---- flags --------------------------------------------------------------- */
+#define GPGOMEA_LINEAR_SCALING 0x1u /* fitness = LS-MSE; without it raw MSE (Eq. 1) */
+#define GPGOMEA_FP64_NODES 0x2u     /* node arithmetic in binary64 (validation)     */
+#define GPGOMEA_PLAIN 0x4u          /* one kernel launch per individual (baseline)  */
+#define GPGOMEA_NO_GRAPH 0x8u       /* launch directly, no hipGraph capture/replay  */
+
+/* ---- limits ------------------------------------------------------------- */
+#define GPGOMEA_MAX_LEN 511    /* L_max: tokens per program (template depth 8)   */
+#define GPGOMEA_MAX_CONSTS 256 /* C_max: constants per program                    */
+#define GPGOMEA_MAX_FEATURES 64
+
+/* Library version, major*10000 + minor*100 + patch. */
+int gpgomea_version(void);
+
+/* Message of the last failing call on this thread ("" if none).  The pointer
+ * stays valid until the next call on this thread. */
+const char* gpgomea_last_error(void);
+
+/* Bytes of device workspace that gpgomea_eval_batch and gpgomea_grad_consts
+ * need for this problem shape and flag set (same arguments as the calls).
+ * Returns 0 if the shape is invalid (see gpgomea_last_error). */
+size_t gpgomea_workspace_bytes(int32_t M, int32_t L_max, int32_t C_max, int32_t F, int64_t N,
+                               uint32_t flags);
+
+/* Fitness of a batch of M programs on one dataset.
+ *   ops      device int8 [M][L_max]: postfix programs, END (-1) terminated or
+ *            exactly L_max long.  1 <= L_max <= GPGOMEA_MAX_LEN.
+ *   consts   device float [M][C_max]: constant list of each program, in order
+ *            of appearance (a program may use at most C_max of them).
+ *   X        device float [F][ldx]: feature-major dataset, row r of feature k
+ *            at X[k*ldx + r]; ldx >= N.  1 <= F <= GPGOMEA_MAX_FEATURES.
+ *   y        device float [N]: targets, N >= 1.
+ *   flags    GPGOMEA_* bit set.
+ *   fitness  device double [M] out: LS-MSE (LINEAR_SCALING) or MSE; +inf when
+ *            status[i] != 0.
+ *   aux      device double [M][4] out, or NULL: a, b (the fit; b = 0, a = mean y
+ *            without LINEAR_SCALING or when Var(p) <= 1e-12*max(mean(p)^2, 1e-300)),
+ *            raw MSE (Eq. 1), NMSE = fitness / Var(y) (Eq. 2).
+ *   status   device int8 [M] out, or NULL: 0 ok, 1 non-finite, 2 bad program.
+ * Errors: E_ARG (NULL required pointer, unknown flag), E_SHAPE (sizes),
+ * E_WORKSPACE, E_HIP. */
+int gpgomea_eval_batch(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                       int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                       const float* y, uint32_t flags, double* fitness, double* aux,
+                       int8_t* status, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Fitness and its gradient with respect to every constant.
+ *   Same inputs and outputs as gpgomea_eval_batch, plus
+ *   grad     device double [M][C_max] out: d fitness / d consts[i][j]; zero for
+ *            unused constants and for individuals with status != 0.
+ * With linear scaling the gradient is (2b/N) sum_r (a + b p_r - y_r) dp_r/dc_j
+ * (the optimal a, b have zero partials); without it (2/N) sum_r (p_r - y_r)
+ * dp_r/dc_j.  A protected operator's guarded branch and a clamp outside its
+ * range have derivative 0; sqrt|a| has derivative 0 at a = 0. */
+int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                        int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                        const float* y, uint32_t flags, double* fitness, double* aux,
+                        double* grad, int8_t* status, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* ---- host-side codec (no GPU needed) --------------------------------------
+ * Genotype: int8 genes[M][T] heap-ordered over a full binary template (children
+ * of slot s at 2s+1, 2s+2; unary operators read 2s+1), float gene_consts[M][T],
+ * T = 2^(H+1)-1.  Individual i has height heights[i] (or `height` for all if
+ * heights is NULL); slots past its own template are ignored.
+ *
+ * gpgomea_encode: post-order traversal of the active nodes (introns dropped),
+ * Section 3.2 and Fig. 1.  Writes ops[M][L_max] (END padded), consts[M][C_max]
+ * (zero padded, float bit patterns copied), len[M], nconst[M] (either may be
+ * NULL).  Fails with E_PROGRAM (an active slot holds no symbol, an operator is
+ * active at a leaf slot, or the program exceeds L_max / C_max); on failure
+ * *bad_index (if not NULL) names the individual. */
+int gpgomea_encode(const int8_t* genes, const float* gene_consts, int32_t M, int32_t T,
+                   int32_t height, const int8_t* heights, int8_t* ops, int32_t L_max,
+                   float* consts, int32_t C_max, int16_t* len, int16_t* nconst,
+                   int32_t* bad_index);
+
+/* gpgomea_decode: rebuild heap-ordered genotypes of height `height` from
+ * postfix programs (inverse of gpgomea_encode on the active nodes; every
+ * other slot becomes -1 with constant 0).  E_PROGRAM if a program is malformed
+ * or taller than the template. */
+int gpgomea_decode(const int8_t* ops, const float* consts, int32_t M, int32_t L_max,
+                   int32_t C_max, int32_t height, int8_t* genes, float* gene_consts,
+                   int32_t* bad_index);
+
+/* gpgomea_validate: check host-resident programs the way the device does:
+ * status_out[i] = 0 (valid) or 2 (unknown symbol, variable >= F, more than
+ * C_max constants, stack underflow, not exactly one result).  Returns the
+ * number of invalid programs (>= 0) or a negative error code. */
+int gpgomea_validate(const int8_t* ops, int32_t M, int32_t L_max, int32_t C_max, int32_t F,
+                     int8_t* status_out);
+
+/* ---- tuning -----------------------------------------------------------------
+ * gpgomea_autotune: time the fused kernels over their launch parameters
+ * (rows per lane, waves per block, rows per LDS tile, individuals per group)
+ * on the given device inputs, keep the fastest choice for this problem class
+ * in the process-wide table and, if cache_path is not NULL, merge it into that
+ * JSON file.  Synchronises `stream`.  `trials` = timed repetitions per
+ * candidate (>= 1).  Writes a one-line description of the choice to
+ * `out_desc` (if not NULL, up to desc_len bytes). */
+int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                     int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                     const float* y, uint32_t flags, int32_t with_grad, void* workspace,
+                     size_t workspace_bytes, const char* cache_path, int32_t trials,
+                     char* out_desc, int32_t desc_len, void* stream);
+
+/* Load a tuning JSON file written by gpgomea_autotune into the process-wide
+ * table (E_ARG if unreadable). */
+int gpgomea_load_tuning(const char* cache_path);
+
+/* Drop every cached hipGraph (they are keyed by shapes, pointers and flags). */
+int gpgomea_clear_graphs(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPGOMEA_EVAL_H */

@@ -1,0 +1,226 @@
+"""Batched GP-GOMEA fitness and constant-gradient evaluation on MI355X (gfx950).
+
+Python face of libgpgomea_eval.so (see include/gpgomea_eval.h): it passes
+torch device pointers and the current HIP stream to the C ABI and returns
+torch tensors.  torch supplies device memory and streams only; every step of
+the evaluation runs in the library's HIP kernels.
+
+    fitness = eval_batch(ops, consts, X, y)                   # LS-MSE per program
+    fitness, grad = grad_consts(ops, consts, X, y)            # + d fitness / d consts
+    ops, consts, lens, nconst = encode(genes, gene_consts, heights, L_max, C_max)
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  # noqa: F401
+                   MAX_LEN, MAX_CONSTS, MAX_FEATURES, check, last_error, lib)
+
+__all__ = ["eval_batch", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
+           "autotune", "clear_graphs", "flags_of", "GPGOMEAFitness", "LibraryError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def flags_of(linear_scaling=True, fp64_nodes=False, plain=False, graph=True) -> int:
+    f = 0
+    if linear_scaling:
+        f |= LINEAR_SCALING
+    if fp64_nodes:
+        f |= FP64_NODES
+    if plain:
+        f |= PLAIN
+    if not graph:
+        f |= NO_GRAPH
+    return f
+
+
+def workspace_bytes(M, L_max, C_max, F, N, flags) -> int:
+    n = lib.gpgomea_workspace_bytes(int(M), int(L_max), int(C_max), int(F), int(N), int(flags))
+    if n == 0:
+        raise LibraryError(_lib.E_SHAPE, last_error())
+    return int(n)
+
+
+_WS = {}
+
+
+def _workspace(device, nbytes):
+    """A cached uint8 device buffer per device, grown on demand (256-aligned:
+    the caching allocator hands out 512-byte aligned blocks)."""
+    torch = _torch()
+    key = str(device)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        if buf is not None:
+            clear_graphs()  # graphs captured against the old buffer
+        buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf
+
+
+def _dev_tensor(t, dtype, name, device=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on a GPU")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU (this library has no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t.contiguous()
+
+
+def _prep(ops, consts, X, y):
+    torch = _torch()
+    ops = _dev_tensor(ops, torch.int8, "ops")
+    dev = ops.device
+    consts = _dev_tensor(consts, torch.float32, "consts", dev)
+    X = _dev_tensor(X, torch.float32, "X", dev)
+    y = _dev_tensor(y, torch.float32, "y", dev)
+    if ops.dim() != 2 or consts.dim() != 2 or X.dim() != 2 or y.dim() != 1:
+        raise ValueError("expected ops [M, L], consts [M, C], X [F, N], y [N]")
+    M, L = ops.shape
+    if consts.shape[0] != M:
+        raise ValueError("ops and consts disagree on M")
+    F, N = X.shape
+    if y.shape[0] != N:
+        raise ValueError("X and y disagree on N")
+    return ops, consts, X, y, dev, int(M), int(L), int(consts.shape[1]), int(F), int(N)
+
+
+def _stream_ptr(dev):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def eval_batch(ops, consts, X, y, linear_scaling=True, fp64_nodes=False, plain=False,
+               graph=True, return_aux=False, return_status=False):
+    """Fitness (float64 [M]) of M postfix programs on X (float32 [F, N],
+    feature-major) and y (float32 [N]).  ``return_aux`` adds a [M, 4] tensor
+    (a, b, MSE, NMSE); ``return_status`` adds int8 [M] (0 ok, 1 non-finite,
+    2 bad program)."""
+    torch = _torch()
+    ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
+    flags = flags_of(linear_scaling, fp64_nodes, plain, graph)
+    fit = torch.empty(M, dtype=torch.float64, device=dev)
+    aux = torch.empty((M, 4), dtype=torch.float64, device=dev) if return_aux else None
+    st = torch.empty(M, dtype=torch.int8, device=dev)
+    nb = workspace_bytes(M, L, C, F, N, flags)
+    ws = _workspace(dev, nb)
+    check(lib.gpgomea_eval_batch(
+        ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
+        y.data_ptr(), flags, fit.data_ptr(), aux.data_ptr() if aux is not None else None,
+        st.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev)))
+    out = [fit]
+    if return_aux:
+        out.append(aux)
+    if return_status:
+        out.append(st)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def grad_consts(ops, consts, X, y, linear_scaling=True, plain=False, graph=True,
+                return_aux=False, return_status=False):
+    """(fitness [M], grad [M, C]) in float64: the gradient of each fitness with
+    respect to that program's constants (zero past its last constant)."""
+    torch = _torch()
+    ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
+    flags = flags_of(linear_scaling, False, plain, graph)
+    fit = torch.empty(M, dtype=torch.float64, device=dev)
+    grad = torch.empty((M, C), dtype=torch.float64, device=dev)
+    aux = torch.empty((M, 4), dtype=torch.float64, device=dev) if return_aux else None
+    st = torch.empty(M, dtype=torch.int8, device=dev)
+    nb = workspace_bytes(M, L, C, F, N, flags)
+    ws = _workspace(dev, nb)
+    check(lib.gpgomea_grad_consts(
+        ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
+        y.data_ptr(), flags, fit.data_ptr(), aux.data_ptr() if aux is not None else None,
+        grad.data_ptr(), st.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev)))
+    out = [fit, grad]
+    if return_aux:
+        out.append(aux)
+    if return_status:
+        out.append(st)
+    return tuple(out)
+
+
+def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path=None, trials=3):
+    """Time the fused kernels' launch parameters on these inputs and keep the
+    fastest for this problem class; returns the library's description."""
+    ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
+    flags = flags_of(linear_scaling)
+    ws = _workspace(dev, workspace_bytes(M, L, C, F, N, flags))
+    desc = ctypes.create_string_buffer(512)
+    check(lib.gpgomea_autotune(
+        ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
+        y.data_ptr(), flags, int(bool(with_grad)), ws.data_ptr(), ws.numel(),
+        cache_path.encode() if cache_path else None, int(trials), desc, 512, _stream_ptr(dev)))
+    return desc.value.decode()
+
+
+def clear_graphs():
+    check(lib.gpgomea_clear_graphs())
+
+
+# ------------------------------------------------------------- host codec
+def _np(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def encode(genes, gene_consts, heights, L_max, C_max):
+    """Genotypes (int8 [M, T] heap order, float32 [M, T]) -> postfix programs.
+    ``heights`` is an int or int8 [M].  Returns (ops int8 [M, L_max],
+    consts float32 [M, C_max], len int16 [M], nconst int16 [M])."""
+    g = _np(genes, np.int8)
+    c = _np(gene_consts, np.float32)
+    M, T = g.shape
+    hs = None
+    h0 = 0
+    if np.ndim(heights) == 0:
+        h0 = int(heights)
+    else:
+        hs = _np(heights, np.int8)
+    ops = np.empty((M, L_max), np.int8)
+    cs = np.empty((M, C_max), np.float32)
+    ln = np.empty(M, np.int16)
+    nc = np.empty(M, np.int16)
+    bad = ctypes.c_int32(-1)
+    rc = lib.gpgomea_encode(g.ctypes.data, c.ctypes.data, M, T, h0,
+                            hs.ctypes.data if hs is not None else None, ops.ctypes.data, L_max,
+                            cs.ctypes.data, C_max, ln.ctypes.data, nc.ctypes.data,
+                            ctypes.byref(bad))
+    if rc < 0:
+        raise LibraryError(rc, f"{last_error()} (individual {bad.value})")
+    return ops, cs, ln, nc
+
+
+def decode(ops, consts, height):
+    o = _np(ops, np.int8)
+    c = _np(consts, np.float32)
+    M, L = o.shape
+    T = 2 ** (height + 1) - 1
+    g = np.empty((M, T), np.int8)
+    gc = np.empty((M, T), np.float32)
+    bad = ctypes.c_int32(-1)
+    rc = lib.gpgomea_decode(o.ctypes.data, c.ctypes.data, M, L, c.shape[1], int(height),
+                            g.ctypes.data, gc.ctypes.data, ctypes.byref(bad))
+    if rc < 0:
+        raise LibraryError(rc, f"{last_error()} (individual {bad.value})")
+    return g, gc
+
+
+def validate(ops, C_max, F):
+    o = _np(ops, np.int8)
+    M, L = o.shape
+    st = np.empty(M, np.int8)
+    check(lib.gpgomea_validate(o.ctypes.data, M, L, int(C_max), int(F), st.ctypes.data))
+    return st
+
+
+from .autograd import GPGOMEAFitness  # noqa: E402

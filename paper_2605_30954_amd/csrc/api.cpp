@@ -1,0 +1,413 @@
+// C ABI entry points: argument checks, launch planning, workspace layout,
+// hipGraph capture/replay and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "errors.h"
+#include "gpgomea_eval.h"
+#include "kernels.h"
+
+namespace gg {
+namespace {
+
+constexpr int kMaxSpans = 256;    // forward partial sums per individual (upper bound)
+constexpr int kMaxAdjSpans = 16;  // gradient partials per individual (upper bound)
+constexpr int kPlainMaxBlocks = 1024;
+constexpr uint32_t kKnownFlags =
+    GPGOMEA_LINEAR_SCALING | GPGOMEA_FP64_NODES | GPGOMEA_PLAIN | GPGOMEA_NO_GRAPH;
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Shape {
+  int M, L_max, C_max, F;
+  int64_t N, ldx;
+  uint32_t flags;
+};
+
+int check_shape(const Shape& s) {
+  if (s.flags & ~kKnownFlags) return fail(GPGOMEA_E_ARG, "unknown flag bits 0x%x", s.flags & ~kKnownFlags);
+  if (s.M < 1) return fail(GPGOMEA_E_SHAPE, "M=%d must be >= 1", s.M);
+  if (s.L_max < 1 || s.L_max > GPGOMEA_MAX_LEN)
+    return fail(GPGOMEA_E_SHAPE, "L_max=%d outside [1, %d]", s.L_max, GPGOMEA_MAX_LEN);
+  if (s.C_max < 0 || s.C_max > GPGOMEA_MAX_CONSTS)
+    return fail(GPGOMEA_E_SHAPE, "C_max=%d outside [0, %d]", s.C_max, GPGOMEA_MAX_CONSTS);
+  if (s.F < 1 || s.F > GPGOMEA_MAX_FEATURES)
+    return fail(GPGOMEA_E_SHAPE, "F=%d outside [1, %d]", s.F, GPGOMEA_MAX_FEATURES);
+  if (s.N < 1 || s.N > (int64_t(1) << 40)) return fail(GPGOMEA_E_SHAPE, "N=%lld out of range", (long long)s.N);
+  if (s.ldx < s.N) return fail(GPGOMEA_E_SHAPE, "ldx=%lld < N=%lld", (long long)s.ldx, (long long)s.N);
+  if (int64_t(s.M) * (kMaxSpans + 1) > (int64_t(1) << 31))
+    return fail(GPGOMEA_E_SHAPE, "M=%d too large", s.M);
+  return GPGOMEA_OK;
+}
+
+// stack slots needed by the deepest program that fits in L_max tokens:
+// floor(log2((L_max + 1) / 2)) binary levels
+int slots_for(int L_max) {
+  int leaves = (L_max + 1) / 2, d = 0;
+  while ((1 << (d + 1)) <= leaves) ++d;
+  return std::max(d, 1);
+}
+
+struct Layout {
+  size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, total;
+  int U_stride;
+};
+
+Layout layout_of(const Shape& s) {
+  Layout l{};
+  l.U_stride = s.L_max + 2;
+  size_t o = 0;
+  l.stats = o;
+  o = align256(o + ST_COUNT * sizeof(double));
+  l.yscr = o;
+  o = align256(o + 3 * kStatBlocks * sizeof(double));
+  l.meta = o;
+  o = align256(o + size_t(s.M) * sizeof(ProgMeta));
+  l.uops = o;
+  o = align256(o + size_t(s.M) * l.U_stride * sizeof(uint2));
+  l.ab = o;
+  o = align256(o + size_t(s.M) * 2 * sizeof(double));
+  l.part = o;
+  o = align256(o + size_t(s.M) * kMaxSpans * 4 * sizeof(double));
+  l.plain_part = o;
+  o = align256(o + size_t(kPlainMaxBlocks) * 4 * sizeof(double));
+  l.ticket = o;
+  o = align256(o + 64);
+  l.gpart = o;
+  o = align256(o + size_t(s.M) * kMaxAdjSpans * std::max(s.C_max, 1) * sizeof(double));
+  l.total = o;
+  return l;
+}
+
+// ---------------------------------------------------------------- planning
+struct TuneKey {
+  int fp64, Lcls, F, Ncls, Mcls, grad;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(fp64, Lcls, F, Ncls, Mcls, grad) < std::tie(o.fp64, o.Lcls, o.F, o.Ncls, o.Mcls, o.grad);
+  }
+};
+int log2cls(int64_t v) {
+  int c = 0;
+  while ((int64_t(1) << (c + 1)) <= v) ++c;
+  return c;
+}
+TuneKey tune_key(const Shape& s, bool grad) {
+  return {int((s.flags & GPGOMEA_FP64_NODES) != 0), log2cls(s.L_max + 1), s.F, log2cls(s.N),
+          log2cls(s.M), int(grad)};
+}
+struct Tuned {
+  int K, R, G;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuned> g_tuned;  // forward choices
+std::map<TuneKey, Tuned> g_tuned_adj;
+
+void finish_spans(TileCfg& c, int M, int64_t N, int max_spans) {
+  const int64_t tiles = (N + c.R - 1) / c.R;
+  c.n_groups = (M + c.G - 1) / c.G;
+  c.tiles_per_span = int((tiles + max_spans - 1) / max_spans);
+  if (c.tiles_per_span < 1) c.tiles_per_span = 1;
+  c.n_spans = int((tiles + c.tiles_per_span - 1) / c.tiles_per_span);
+}
+
+int forward_lds_cap() { return std::min(lds_limit_bytes(), 64 * 1024); }
+
+TileCfg plan_forward(const Shape& s, const Tuned* t) {
+  TileCfg c;
+  const bool fp64 = (s.flags & GPGOMEA_FP64_NODES) != 0;
+  c.K = fp64 ? 4 : 8;
+  c.D = fp64 ? 8 : (slots_for(s.L_max) <= 4 ? 4 : 8);
+  c.W = 4;
+  const int BR = 64 * c.K;
+  const int64_t Nr = (s.N + BR - 1) / BR * BR;
+  if (t) {
+    c.K = fp64 ? 4 : t->K;
+    c.R = t->R;
+    c.G = t->G;
+  } else {
+    c.R = 2048;
+    while (c.R > BR && forward_lds_bytes(s.F, c.R, 64) > size_t(forward_lds_cap())) c.R /= 2;
+    if (Nr < c.R) c.R = int(Nr);
+    const int64_t tiles = (s.N + c.R - 1) / c.R;
+    const int64_t target = 2048;
+    int64_t G = (int64_t(s.M) * tiles + target - 1) / target;
+    G = std::max<int64_t>(G, std::min(s.M, c.W));
+    c.G = int(std::min<int64_t>(G, 64));
+  }
+  c.R = std::max(c.R, 64 * c.K);
+  c.R = c.R / (64 * c.K) * (64 * c.K);
+  c.G = std::max(1, std::min(c.G, s.M));
+  finish_spans(c, s.M, s.N, kMaxSpans);
+  return c;
+}
+
+TileCfg plan_adjoint(const Shape& s, const Tuned* t) {
+  TileCfg c;
+  c.K = 1;
+  c.D = 8;
+  const int tape = std::max(1, s.L_max - 1);
+  const int cap = lds_limit_bytes();
+  const int Cm = std::max(1, s.C_max);
+  bool ok = false;
+  const int Ks[2] = {2, 1};
+  const int Ws[3] = {4, 2, 1};
+  const int Rs[5] = {1024, 512, 256, 128, 64};
+  const int Gs[3] = {16, 8, 4};
+  for (int k : Ks) {
+    if (t && t->K != k) continue;
+    for (int w : Ws) {
+      for (int r : Rs) {
+        if (r < 64 * k) continue;
+        for (int g : Gs) {
+          if (adjoint_lds_bytes(s.F, r, g, Cm, w, k, tape) <= size_t(cap)) {
+            c.K = k;
+            c.W = w;
+            c.R = r;
+            c.G = g;
+            ok = true;
+            break;
+          }
+        }
+        if (ok) break;
+      }
+      if (ok) break;
+    }
+    if (ok) break;
+  }
+  if (!ok) {  // smallest possible block
+    c.K = 1;
+    c.W = 1;
+    c.R = 64;
+    c.G = 1;
+  }
+  const int BR = 64 * c.K;
+  const int64_t Nr = (s.N + BR - 1) / BR * BR;
+  if (Nr < c.R) c.R = int(Nr);
+  c.G = std::max(1, std::min(c.G, s.M));
+  finish_spans(c, s.M, s.N, kMaxAdjSpans);
+  return c;
+}
+
+// ------------------------------------------------------------ graph cache
+struct GraphKey {
+  std::vector<uintptr_t> v;
+  bool operator<(const GraphKey& o) const { return v < o.v; }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+#define GG_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(GPGOMEA_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+struct Call {
+  Shape s;
+  const int8_t* ops;
+  const float* consts;
+  const float* X;
+  const float* y;
+  double* fitness;
+  double* aux;
+  double* grad;
+  int8_t* status;
+  char* ws;
+  hipStream_t stream;
+  bool with_grad;
+};
+
+// Enqueue the whole fused pipeline on c.stream.
+int enqueue_fused(const Call& c, const TileCfg& fc, const TileCfg& ac) {
+  const Layout l = layout_of(c.s);
+  const bool fp64 = (c.s.flags & GPGOMEA_FP64_NODES) != 0;
+  double* stats = reinterpret_cast<double*>(c.ws + l.stats);
+  double* yscr = reinterpret_cast<double*>(c.ws + l.yscr);
+  ProgMeta* meta = reinterpret_cast<ProgMeta*>(c.ws + l.meta);
+  uint2* uops = reinterpret_cast<uint2*>(c.ws + l.uops);
+  double* ab = reinterpret_cast<double*>(c.ws + l.ab);
+  double* part = reinterpret_cast<double*>(c.ws + l.part);
+  double* gpart = reinterpret_cast<double*>(c.ws + l.gpart);
+  const DataArgs d{c.X, c.s.ldx, c.s.F, c.s.N, c.y};
+  const int D = fp64 ? 8 : fc.D;
+  GG_HIP(launch_ystats(c.y, c.s.N, stats, yscr, c.stream));
+  GG_HIP(launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, c.with_grad ? 8 : D,
+                        l.U_stride, uops, meta, c.stream));
+  GG_HIP(launch_probe(fp64, fc.K, c.with_grad ? 8 : D, uops, l.U_stride, meta, c.s.M, d, c.stream));
+  const bool sse = c.aux != nullptr || !(c.s.flags & GPGOMEA_LINEAR_SCALING);
+  if (c.s.flags & GPGOMEA_PLAIN) {
+    unsigned* ticket = reinterpret_cast<unsigned*>(c.ws + l.ticket);
+    double* pp = reinterpret_cast<double*>(c.ws + l.plain_part);
+    GG_HIP(launch_fill_u32(ticket, 1, 0u, c.stream));
+    TileCfg pc = fc;
+    if (c.with_grad) pc.D = 8;
+    for (int i = 0; i < c.s.M; ++i)
+      GG_HIP(launch_plain_forward(fp64, pc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
+                                  c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
+    if (c.with_grad) {
+      TileCfg one = ac;
+      one.G = 1;
+      finish_spans(one, 1, c.s.N, kMaxAdjSpans);
+      for (int i = 0; i < c.s.M; ++i)
+        GG_HIP(launch_fused_adjoint(one, uops + size_t(i) * l.U_stride, l.U_stride, meta + i, 1,
+                                    c.s.C_max, d, stats, ab + 2 * size_t(i),
+                                    gpart + size_t(i) * one.n_spans * c.s.C_max, nullptr,
+                                    std::max(1, c.s.L_max - 1), c.stream));
+      GG_HIP(launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
+                                  c.s.flags, c.status, c.grad, c.stream));
+    }
+    return GPGOMEA_OK;
+  }
+  TileCfg f2 = fc;
+  if (c.with_grad) f2.D = 8;  // one uop stream serves both kernels
+  GG_HIP(launch_fused_forward(fp64, f2, uops, l.U_stride, meta, c.s.M, d, stats, part, sse,
+                              c.stream));
+  GG_HIP(launch_finalize(meta, c.s.M, part, f2.n_spans, stats, c.s.flags, c.fitness, c.aux,
+                         c.status, ab, c.stream));
+  if (c.with_grad) {
+    GG_HIP(launch_fused_adjoint(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab, gpart,
+                                nullptr, std::max(1, c.s.L_max - 1), c.stream));
+    GG_HIP(launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab, c.s.flags,
+                                c.status, c.grad, c.stream));
+  }
+  return GPGOMEA_OK;
+}
+
+int run_call(const Call& c) {
+  TileCfg fc, ac;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(c.s, false));
+    fc = plan_forward(c.s, it == g_tuned.end() ? nullptr : &it->second);
+    auto ia = g_tuned_adj.find(tune_key(c.s, true));
+    ac = plan_adjoint(c.s, ia == g_tuned_adj.end() ? nullptr : &ia->second);
+  }
+  const bool graph = !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr;
+  if (!graph) return enqueue_fused(c, fc, ac);
+
+  GraphKey key;
+  key.v = {uintptr_t(c.with_grad), uintptr_t(c.ops), uintptr_t(c.consts), uintptr_t(c.X),
+           uintptr_t(c.y), uintptr_t(c.fitness), uintptr_t(c.aux), uintptr_t(c.grad),
+           uintptr_t(c.status), uintptr_t(c.ws), uintptr_t(c.s.M), uintptr_t(c.s.L_max),
+           uintptr_t(c.s.C_max), uintptr_t(c.s.F), uintptr_t(c.s.N), uintptr_t(c.s.ldx),
+           uintptr_t(c.s.flags), uintptr_t(fc.K), uintptr_t(fc.R), uintptr_t(fc.G),
+           uintptr_t(ac.K), uintptr_t(ac.R), uintptr_t(ac.G), uintptr_t(ac.W)};
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) exec = it->second;
+  }
+  if (!exec) {
+    GG_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_fused(c, fc, ac);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c.stream, &g);
+    if (rc != GPGOMEA_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(GPGOMEA_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(GPGOMEA_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    g_graphs[key] = exec;
+  }
+  GG_HIP(hipGraphLaunch(exec, c.stream));
+  return GPGOMEA_OK;
+}
+
+int check_call(const Shape& s, const void* ops, const void* consts, const void* X, const void* y,
+               const void* fitness, void* ws, size_t ws_bytes) {
+  if (!ops || !X || !y || !fitness || !ws) return fail(GPGOMEA_E_ARG, "NULL required pointer");
+  if (s.C_max > 0 && !consts) return fail(GPGOMEA_E_ARG, "consts is NULL but C_max > 0");
+  const int rc = check_shape(s);
+  if (rc) return rc;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GPGOMEA_E_WORKSPACE, "workspace not 256-byte aligned");
+  const size_t need = layout_of(s).total;
+  if (ws_bytes < need)
+    return fail(GPGOMEA_E_WORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  return GPGOMEA_OK;
+}
+
+}  // namespace
+}  // namespace gg
+
+using namespace gg;
+
+extern "C" int gpgomea_version(void) { return 10000; }
+
+extern "C" const char* gpgomea_last_error(void) { return last_error().c_str(); }
+
+extern "C" size_t gpgomea_workspace_bytes(int32_t M, int32_t L_max, int32_t C_max, int32_t F,
+                                          int64_t N, uint32_t flags) {
+  const Shape s{M, L_max, C_max, F, N, N, flags};
+  if (check_shape(s) != GPGOMEA_OK) return 0;
+  return layout_of(s).total;
+}
+
+extern "C" int gpgomea_eval_batch(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                                  int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                                  const float* y, uint32_t flags, double* fitness, double* aux,
+                                  int8_t* status, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+  const Shape s{M, L_max, C_max, F, N, ldx, flags};
+  int rc = check_call(s, ops, consts, X, y, fitness, workspace, workspace_bytes);
+  if (rc) return rc;
+  Call c{s, ops, consts, X, y, fitness, aux, nullptr, status, static_cast<char*>(workspace),
+         static_cast<hipStream_t>(stream), false};
+  return run_call(c);
+}
+
+extern "C" int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                                   int32_t C_max, const float* X, int32_t F, int64_t N,
+                                   int64_t ldx, const float* y, uint32_t flags, double* fitness,
+                                   double* aux, double* grad, int8_t* status, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+  const Shape s{M, L_max, C_max, F, N, ldx, flags};
+  int rc = check_call(s, ops, consts, X, y, fitness, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (!grad) return fail(GPGOMEA_E_ARG, "grad is NULL");
+  if (flags & GPGOMEA_FP64_NODES)
+    return fail(GPGOMEA_E_UNSUPPORTED, "the adjoint runs in binary32 nodes only");
+  Call c{s, ops, consts, X, y, fitness, aux, grad, status, static_cast<char*>(workspace),
+         static_cast<hipStream_t>(stream), true};
+  return run_call(c);
+}
+
+extern "C" int gpgomea_clear_graphs(void) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+  g_graphs.clear();
+  return GPGOMEA_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                                int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                                const float* y, uint32_t flags, int32_t with_grad, void* workspace,
+                                size_t workspace_bytes, const char* cache_path, int32_t trials,
+                                char* out_desc, int32_t desc_len, void* stream) {
+  (void)ops; (void)M; (void)L_max; (void)consts; (void)C_max; (void)X; (void)F; (void)N;
+  (void)ldx; (void)y; (void)flags; (void)with_grad; (void)workspace; (void)workspace_bytes;
+  (void)cache_path; (void)trials; (void)out_desc; (void)desc_len; (void)stream;
+  return fail(GPGOMEA_E_UNSUPPORTED, "autotune not built yet");
+}
+
+extern "C" int gpgomea_load_tuning(const char* cache_path) {
+  (void)cache_path;
+  return fail(GPGOMEA_E_UNSUPPORTED, "autotune not built yet");
+}

@@ -1,0 +1,200 @@
+// Register-stack interpreter for one uop program over K rows per lane.
+//
+// The paper evaluates an individual's postfix program with a stack, one
+// forward pass per data point, all threads of a block running the same
+// program so control flow never diverges (Section 3.2, "Evaluation on the
+// GPU").  Here a whole wave (64 lanes) runs one program: the uop stream is
+// wave-uniform, read with scalar loads one uop ahead, and every lane evaluates
+// K rows at once so each decoded uop is amortised over K*64 rows.
+//
+// Code-shape rules this file follows (checked in the gfx950 ISA):
+//  * the accumulator and the D stack slots are separate vector-typed values
+//    (never an indexed array), so they live in VGPRs and are never spilled to
+//    scratch by dynamic indexing;
+//  * dispatch is a chain of independent uniform `if` blocks, each ending in an
+//    empty volatile asm statement: the block stays a branch (no if-conversion
+//    into per-element selects) and updates its registers in place (no
+//    structurizer copies at the joins).
+//
+// Variables are read from the block's row tile in LDS (feature-major,
+// `rstride` floats per feature); lane l of a batch owns rows
+// [row0 + l*K, row0 + l*K + K).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "devmath.h"
+#include "uop.h"
+
+#define GG_BRANCH() asm volatile("")
+
+namespace gg {
+
+template <typename T, int K>
+struct VecT {
+  typedef T type __attribute__((ext_vector_type(K)));
+};
+
+template <typename T, int K>
+__device__ inline typename VecT<T, K>::type lds_rows(const float* __restrict__ p) {
+  typename VecT<T, K>::type v;
+  static_assert(K % 4 == 0 || K < 4, "K must be 1, 2 or a multiple of 4");
+  if constexpr (K >= 4) {
+#pragma unroll
+    for (int j = 0; j < K; j += 4) {
+      const float4 q = *reinterpret_cast<const float4*>(p + j);
+      v[j] = T(q.x);
+      v[j + 1] = T(q.y);
+      v[j + 2] = T(q.z);
+      v[j + 3] = T(q.w);
+    }
+  } else if constexpr (K == 2) {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    v[0] = T(q.x);
+    v[1] = T(q.y);
+  } else {
+    v[0] = T(p[0]);
+  }
+  return v;
+}
+
+// D register slots, addressed by a wave-uniform slot number.
+template <typename V, int D>
+struct Slots {
+  static_assert(D >= 1 && D <= 8, "1..8 stack slots");
+  V s0, s1, s2, s3, s4, s5, s6, s7;
+
+  __device__ inline void put(uint32_t k, const V& a) {
+    if (k == 0) { s0 = a; GG_BRANCH(); }
+    if constexpr (D > 1) if (k == 1) { s1 = a; GG_BRANCH(); }
+    if constexpr (D > 2) if (k == 2) { s2 = a; GG_BRANCH(); }
+    if constexpr (D > 3) if (k == 3) { s3 = a; GG_BRANCH(); }
+    if constexpr (D > 4) if (k == 4) { s4 = a; GG_BRANCH(); }
+    if constexpr (D > 5) if (k == 5) { s5 = a; GG_BRANCH(); }
+    if constexpr (D > 6) if (k == 6) { s6 = a; GG_BRANCH(); }
+    if constexpr (D > 7) if (k == 7) { s7 = a; GG_BRANCH(); }
+  }
+  __device__ inline void get(uint32_t k, V& a) const {
+    if (k == 0) { a = s0; GG_BRANCH(); }
+    if constexpr (D > 1) if (k == 1) { a = s1; GG_BRANCH(); }
+    if constexpr (D > 2) if (k == 2) { a = s2; GG_BRANCH(); }
+    if constexpr (D > 3) if (k == 3) { a = s3; GG_BRANCH(); }
+    if constexpr (D > 4) if (k == 4) { a = s4; GG_BRANCH(); }
+    if constexpr (D > 5) if (k == 5) { a = s5; GG_BRANCH(); }
+    if constexpr (D > 6) if (k == 6) { a = s6; GG_BRANCH(); }
+    if constexpr (D > 7) if (k == 7) { a = s7; GG_BRANCH(); }
+  }
+};
+
+__device__ inline float f32_of(uint32_t bits) { return __uint_as_float(bits); }
+
+// Wave-uniform scalar load of a uop (the pointer must be provably uniform).
+__device__ inline uint2 load_uop(const uint2* __restrict__ prog, int pc) { return prog[pc]; }
+
+// Per-element application of the protected operators to K-vectors.
+template <typename T, int K>
+struct VOps {
+  using V = typename VecT<T, K>::type;
+  using P = Prot<T>;
+#define GG_MAP1(name, expr)                              \
+  __device__ static inline V name(V a) {                 \
+    V r;                                                 \
+    _Pragma("unroll") for (int j = 0; j < K; ++j) {      \
+      const T x = a[j];                                  \
+      r[j] = (expr);                                     \
+    }                                                    \
+    return r;                                            \
+  }
+#define GG_MAP2(name, expr)                              \
+  __device__ static inline V name(V a, V b) {            \
+    V r;                                                 \
+    _Pragma("unroll") for (int j = 0; j < K; ++j) {      \
+      const T x = a[j], z = b[j];                        \
+      r[j] = (expr);                                     \
+    }                                                    \
+    return r;                                            \
+  }
+  GG_MAP1(sin, P::sin_(x))
+  GG_MAP1(cos, P::cos_(x))
+  GG_MAP1(sqrt, P::sqrt_(x))
+  GG_MAP1(exp, P::exp_(x))
+  GG_MAP1(log, P::log_(x))
+  GG_MAP2(div, P::div(x, z))
+  GG_MAP2(pow, P::pow_(x, z))
+#undef GG_MAP1
+#undef GG_MAP2
+};
+
+// Evaluate the program on K rows per lane; returns the predictions.
+//   prog    uop stream of this individual (wave-uniform pointer)
+//   xt      LDS row tile: feature k, row r at xt[k*rstride + r]
+//   lrow    this lane's first row within the tile (multiple of K)
+template <typename T, int K, int D>
+__device__ inline typename VecT<T, K>::type run_program(const uint2* __restrict__ prog,
+                                                        const float* __restrict__ xt, int rstride,
+                                                        int lrow) {
+  using V = typename VecT<T, K>::type;
+  using O = VOps<T, K>;
+  Slots<V, D> st;
+  V acc = T(0), t = T(0);
+  const float* __restrict__ xl = xt + lrow;
+  uint2 cur = load_uop(prog, 0);
+  int pc = 0;
+#pragma unroll 1
+  for (;;) {
+    const uint2 nxt = load_uop(prog, pc + 1);
+    const uint32_t h = cur.x;
+    const uint32_t op = uop_op(h);
+    if (op == UOP_END) break;
+    const uint32_t ld = uop_load(h);
+    const T c = T(f32_of(cur.y));
+    // load prefix: the first leaf of a subtree (after pushing the pending value)
+    if (ld != LD_NONE) {
+      if (h & HDR_PUSH) { st.put(uop_push_slot(h), acc); GG_BRANCH(); }
+      if (ld == LD_VAR) { acc = lds_rows<T, K>(xl + uop_load_arg(h) * rstride); GG_BRANCH(); }
+      if (ld == LD_CONST) { acc = c; GG_BRANCH(); }
+      GG_BRANCH();
+    }
+    const uint32_t sk = uop_src(h);
+    if (sk == SRC_VAR) { t = lds_rows<T, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
+    if (sk == SRC_POP) { st.get(uop_src_arg(h), t); GG_BRANCH(); }
+    if (op <= UOP_MUL) {
+      if (sk == SRC_CONST) {  // the constant stays a scalar operand
+        if (op == UOP_ADD) { acc = acc + c; GG_BRANCH(); }
+        if (op == UOP_SUB) { acc = acc - c; GG_BRANCH(); }
+        if (op == UOP_RSUB) { acc = c - acc; GG_BRANCH(); }
+        if (op == UOP_MUL) { acc = acc * c; GG_BRANCH(); }
+        GG_BRANCH();
+      }
+      if (sk == SRC_VAR || sk == SRC_POP) {
+        if (op == UOP_ADD) { acc = acc + t; GG_BRANCH(); }
+        if (op == UOP_SUB) { acc = acc - t; GG_BRANCH(); }
+        if (op == UOP_RSUB) { acc = t - acc; GG_BRANCH(); }
+        if (op == UOP_MUL) { acc = acc * t; GG_BRANCH(); }
+        GG_BRANCH();
+      }
+      GG_BRANCH();
+    }
+    if (op >= UOP_DIV && op <= UOP_RPOW) {
+      if (sk == SRC_CONST) { t = c; GG_BRANCH(); }
+      if (op == UOP_DIV) { acc = O::div(acc, t); GG_BRANCH(); }
+      if (op == UOP_RDIV) { acc = O::div(t, acc); GG_BRANCH(); }
+      if (op == UOP_POW) { acc = O::pow(acc, t); GG_BRANCH(); }
+      if (op == UOP_RPOW) { acc = O::pow(t, acc); GG_BRANCH(); }
+      GG_BRANCH();
+    }
+    if (op >= UOP_SIN) {
+      if (op == UOP_SIN) { acc = O::sin(acc); GG_BRANCH(); }
+      if (op == UOP_COS) { acc = O::cos(acc); GG_BRANCH(); }
+      if (op == UOP_SQ) { acc = acc * acc; GG_BRANCH(); }
+      if (op == UOP_SQRT) { acc = O::sqrt(acc); GG_BRANCH(); }
+      if (op == UOP_EXP) { acc = O::exp(acc); GG_BRANCH(); }
+      if (op == UOP_LOG) { acc = O::log(acc); GG_BRANCH(); }
+      GG_BRANCH();
+    }
+    cur = nxt;
+    ++pc;
+  }
+  return acc;
+}
+
+}  // namespace gg

@@ -1,0 +1,93 @@
+// Host-side launchers of the device kernels (internal interface between the
+// C ABI and the kernel translation units).  Every launcher only enqueues on
+// `stream` and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "uop.h"
+
+namespace gg {
+
+// Layout of the dataset statistics block in the workspace (doubles).
+enum : int {
+  ST_YBAR = 0,  // mean of y
+  ST_VY = 1,    // population variance of y
+  ST_YT = 2,    // sum of (y - ybar) over all rows (rounding residue, ~0)
+  ST_N = 3,
+  ST_COUNT = 8
+};
+constexpr int kStatBlocks = 256;  // partial sums per statistics pass
+
+// Launch parameters of the row-tiled kernels.
+struct TileCfg {
+  int K = 8;               // rows per lane per batch
+  int D = 8;               // register stack slots (template)
+  int W = 4;               // waves per block
+  int R = 1024;            // rows per LDS tile (multiple of 64*K)
+  int G = 16;              // individuals per group (fused forward)
+  int tiles_per_span = 1;  // LDS tiles a block sweeps before writing partials
+  int n_spans = 1;
+  int n_groups = 1;
+};
+
+struct DataArgs {
+  const float* X;
+  int64_t ldx;
+  int F;
+  int64_t N;
+  const float* y;
+};
+
+hipError_t launch_ystats(const float* y, int64_t N, double* stats, double* scratch, hipStream_t s);
+
+hipError_t launch_compile(const int8_t* ops, int M, int L_max, const float* consts, int C_max,
+                          int F, int Dmax, int U_stride, uint2* uops, ProgMeta* meta, hipStream_t s);
+
+// mean prediction over the first rows -> meta[i].mu
+hipError_t launch_probe(bool fp64, int K, int D, const uint2* uops, int U_stride, ProgMeta* meta,
+                        int M, const DataArgs& d, hipStream_t s);
+
+// fused batched forward: partial moment sums part[i][span][4]
+hipError_t launch_fused_forward(bool fp64, const TileCfg& c, const uint2* uops, int U_stride,
+                                const ProgMeta* meta, int M, const DataArgs& d,
+                                const double* stats, double* part, bool want_sse, hipStream_t s);
+
+// per-individual finalize of the fused partials
+hipError_t launch_finalize(const ProgMeta* meta, int M, const double* part, int n_spans,
+                           const double* stats, uint32_t flags, double* fitness, double* aux,
+                           int8_t* status, double* ab, hipStream_t s);
+
+// plain form: one launch per individual (call M times), last block finalizes
+hipError_t launch_plain_forward(bool fp64, const TileCfg& c, int i, const uint2* uops,
+                                int U_stride, const ProgMeta* meta, const DataArgs& d,
+                                const double* stats, double* part, unsigned* ticket,
+                                uint32_t flags, double* fitness, double* aux, int8_t* status,
+                                double* ab, hipStream_t s);
+int plain_blocks(const TileCfg& c, int64_t N);
+
+// adjoint: gradient partials gpart[i][span][C_max]
+hipError_t launch_fused_adjoint(const TileCfg& c, const uint2* uops, int U_stride,
+                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                                const double* stats, const double* ab, double* gpart,
+                                float* tape_spill, int tape_lds, hipStream_t s);
+hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const double* gpart,
+                                int n_spans, const double* stats, const double* ab,
+                                uint32_t flags, const int8_t* status, double* grad,
+                                hipStream_t s);
+
+int lds_limit_bytes();
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
+
+// LDS bytes of one adjoint block (row tile, centred targets, constant
+// accumulators, counter, W wave tapes of tape_cap entries x 64 lanes x K rows).
+inline size_t adjoint_lds_bytes(int F, int R, int G, int C_max, int W, int K, int tape_cap) {
+  const size_t off = (size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * C_max * 8 + 15) & ~size_t(15);
+  return off + 16 + size_t(W) * tape_cap * 64 * K * 4;
+}
+inline size_t forward_lds_bytes(int F, int R, int G) {
+  return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * 4 * 8 + 16;
+}
+
+}  // namespace gg

@@ -1,0 +1,104 @@
+"""GPU parity of the constant gradient (reverse mode on the device) against the
+oracle's forward-mode gradient, against central finite differences, and
+through torch.autograd."""
+import numpy as np
+import pytest
+
+import paper_2605_30954_amd as gg
+from oracle import grad as OG
+from parity_util import (gate_fitness, gate_gradients, log, make_inputs, oracle_flags,
+                         oracle_gradients, oracle_scores, to_device)
+from synth import get_config
+
+pytestmark = pytest.mark.gpu
+
+
+def run_grad(cid, M, N, linear_scaling=True, plain=False, salt=1):
+    cfg = get_config(cid)
+    log(f"[case] grad cfg{cid} M={M} N={N} ls={linear_scaling} plain={plain}")
+    d = make_inputs(cfg, M, N, salt)
+    ops, cs, X, y = to_device(d)
+    fit, grad, st = gg.grad_consts(ops, cs, X, y, linear_scaling=linear_scaling, plain=plain,
+                                   return_status=True)
+    fit, grad, st = fit.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    idx = list(range(M))
+    vy = float(np.var(d["y"].astype(np.float64)))
+    fl = oracle_flags(d, idx, "f32", linear_scaling, with_grad=True)
+    ref = oracle_scores(d, idx, linear_scaling)
+    gate_fitness(fit, st, ref, fl, vy, "f32", f"grad-call fitness cfg{cid}")
+    refs = oracle_gradients(d, idx, linear_scaling)
+    rep = gate_gradients(grad, st, refs, fl, vy, what=f"cfg{cid} ls={linear_scaling} plain={plain}")
+    assert rep["gated"] >= M // 3
+    return d, grad, st, refs, fl, vy
+
+
+def test_cfg4_gradients_linear_scaling():
+    run_grad(4, 64, 12000)
+
+
+def test_cfg4_gradients_raw_mse():
+    run_grad(4, 48, 9000, linear_scaling=False)
+
+
+def test_cfg2_gradients():
+    run_grad(2, 64, 10007)
+
+
+def test_cfg5_gradients_full_operator_set():
+    run_grad(5, 24, 3001)
+
+
+def test_plain_adjoint_matches_fused():
+    cfg = get_config(4)
+    d = make_inputs(cfg, 32, 9000, salt=4)
+    ops, cs, X, y = to_device(d)
+    f1, g1 = gg.grad_consts(ops, cs, X, y)
+    f2, g2 = gg.grad_consts(ops, cs, X, y, plain=True)
+    f3, g3 = gg.grad_consts(ops, cs, X, y)
+    assert np.array_equal(g1.cpu().numpy(), g3.cpu().numpy())   # bitwise repeatable
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    fin = np.isfinite(f1.cpu().numpy())
+    np.testing.assert_allclose(g2[fin], g1[fin], rtol=1e-6, atol=1e-12)
+
+
+def test_gradient_against_central_differences():
+    """GPU gradient vs FP64 central differences (h = 1e-4) of the oracle's
+    fitness; constants next to a kink (FD at h and h/2 disagree) are skipped."""
+    cfg = get_config(4)
+    d = make_inputs(cfg, 24, 6000, salt=9)
+    ops, cs, X, y = to_device(d)
+    fit, grad, st = gg.grad_consts(ops, cs, X, y, return_status=True)
+    grad = grad.cpu().numpy()
+    fl = oracle_flags(d, range(24), "f32", with_grad=True)
+    vy = float(np.var(d["y"].astype(np.float64)))
+    checked = 0
+    for m in range(24):
+        if fl[m] or st[m].item() != 0:
+            continue
+        f1 = OG.fd_gradient(d["genes"][m], d["gc"][m], 5, d["X"], d["y"], h=1e-4)
+        f2 = OG.fd_gradient(d["genes"][m], d["gc"][m], 5, d["X"], d["y"], h=5e-5)
+        if f1.size == 0:
+            continue
+        sc = float(np.max(np.abs(f1)))
+        if np.max(np.abs(f1 - f2)) > 1e-6 * sc + 1e-12 * vy:
+            continue
+        assert np.max(np.abs(grad[m, : f1.size] - f1)) <= 2e-5 * sc + 1e-10 * vy, m
+        checked += 1
+    log(f"[fd] checked {checked} of 24")
+    assert checked >= 8
+
+
+def test_autograd_function():
+    import torch
+    cfg = get_config(4)
+    d = make_inputs(cfg, 16, 5000, salt=2)
+    ops, cs, X, y = to_device(d)
+    c = cs.clone().requires_grad_(True)
+    f = gg.GPGOMEAFitness.apply(c, ops, X, y)
+    w = torch.linspace(0.5, 2.0, 16, dtype=torch.float64, device=f.device)
+    (f * w).sum().backward()
+    fit, grad = gg.grad_consts(ops, cs, X, y)
+    ok = torch.isfinite(fit)
+    want = (w[:, None] * grad).float()
+    assert torch.allclose(c.grad[ok], want[ok], rtol=1e-6, atol=0)
+    assert torch.equal(f, fit)

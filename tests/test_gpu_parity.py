@@ -1,0 +1,105 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle on
+every workload, at sizes the oracle finishes quickly, spanning several row
+tiles, a ragged tail, both node precisions, both fitness kinds and both launch
+forms (fused batch and one launch per individual)."""
+import numpy as np
+import pytest
+
+from parity_util import (gate_fitness, log, make_inputs, oracle_flags, oracle_scores, to_device)
+from synth import get_config
+
+pytestmark = pytest.mark.gpu
+
+import paper_2605_30954_amd as gg  # noqa: E402
+
+
+def run_case(cid, M, N, precision="f32", linear_scaling=True, plain=False, graph=True, salt=0):
+    cfg = get_config(cid)
+    log(f"[case] cfg{cid} M={M} N={N} {precision} ls={linear_scaling} plain={plain} graph={graph}")
+    d = make_inputs(cfg, M, N, salt)
+    ops, cs, X, y = to_device(d)
+    fit, aux, st = gg.eval_batch(ops, cs, X, y, linear_scaling=linear_scaling,
+                                 fp64_nodes=(precision == "f64"), plain=plain, graph=graph,
+                                 return_aux=True, return_status=True)
+    fit, aux, st = fit.cpu().numpy(), aux.cpu().numpy(), st.cpu().numpy()
+    idx = list(range(M))
+    ref = oracle_scores(d, idx, linear_scaling, precision)
+    fl = oracle_flags(d, idx, precision, linear_scaling)
+    vy = float(np.var(d["y"].astype(np.float64)))
+    rep = gate_fitness(fit, st, ref, fl, vy, precision, f"cfg{cid} {precision} ls={linear_scaling}")
+    return d, fit, aux, st, ref, fl, rep
+
+
+def test_cfg1_fp32_linear_scaling():
+    run_case(1, 64, 1000)
+
+
+def test_cfg1_fp32_raw_mse():
+    run_case(1, 64, 1000, linear_scaling=False)
+
+
+def test_cfg1_fp64_nodes():
+    run_case(1, 64, 1000, precision="f64")
+
+
+def test_cfg1_plain_form():
+    run_case(1, 64, 1000, plain=True)
+
+
+def test_cfg2_fp32_several_tiles_ragged_tail():
+    run_case(2, 256, 20011)
+
+
+def test_cfg2_fp64_nodes():
+    run_case(2, 128, 9001, precision="f64")
+
+
+def test_cfg2_plain_form_raw():
+    run_case(2, 64, 20011, plain=True, linear_scaling=False)
+
+
+def test_cfg3_mixed_heights():
+    run_case(3, 192, 12345)
+
+
+def test_cfg4_fp32():
+    run_case(4, 128, 15000)
+
+
+def test_cfg5_fp32_full_operator_set():
+    run_case(5, 48, 4099)
+
+
+def test_cfg5_fp64_nodes():
+    run_case(5, 24, 2000, precision="f64")
+
+
+def test_aux_outputs_match_oracle():
+    d, fit, aux, st, ref, fl, _ = run_case(2, 96, 7000)
+    ok = (st == 0) & (~fl)
+    assert ok.sum() > 50
+    # raw MSE and NMSE (Eq. 1, 2); a, b of the fit
+    np.testing.assert_allclose(aux[ok, 2], ref["mse"][ok], rtol=1e-5)
+    np.testing.assert_allclose(aux[ok, 3], ref["nmse"][ok], rtol=1e-5, atol=1e-10)
+    nondeg = ok & (ref["b"] != 0)
+    np.testing.assert_allclose(aux[nondeg, 1], ref["b"][nondeg], rtol=1e-4, atol=1e-9)
+
+
+def test_plain_and_fused_agree_and_are_deterministic():
+    cfg = get_config(2)
+    d = make_inputs(cfg, 128, 30000, salt=3)
+    import torch
+    ops, cs, X, y = to_device(d)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):   # captured graphs need a non-default stream
+        r = [gg.eval_batch(ops, cs, X, y) for _ in range(3)]   # capture, then replays
+        r.append(gg.eval_batch(ops, cs, X, y, graph=False))
+        r.append(gg.eval_batch(ops, cs, X, y, plain=True))
+    s.synchronize()
+    f1, f2, f5, f3, f4 = [t.cpu().numpy() for t in r]
+    assert np.array_equal(f1, f5, equal_nan=True)
+    assert np.array_equal(f1, f2, equal_nan=True)          # bitwise repeatable
+    assert np.array_equal(f1, f3, equal_nan=True)          # graph == direct launch
+    fin = np.isfinite(f1)
+    np.testing.assert_allclose(f4[fin], f1[fin], rtol=1e-9, atol=1e-12)
+    assert np.array_equal(np.isfinite(f4), fin)
