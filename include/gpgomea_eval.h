@@ -171,6 +171,26 @@ int gpgomea_load_tuning(const char* cache_path);
 /* Drop every cached hipGraph (they are keyed by shapes, pointers and flags). */
 int gpgomea_clear_graphs(void);
 
+/* ---- measurement -------------------------------------------------------------
+ * gpgomea_profile(1): every kernel a later call enqueues is bracketed by a pair
+ * of hipEvents on that call's stream (hipGraph capture is bypassed meanwhile);
+ * gpgomea_profile(0) stops.  gpgomea_profile_report writes one line per
+ * kernel kind, "name launches total_ms\n", for everything recorded since the
+ * previous report (it waits for those events), and clears the record.  With
+ * buf == NULL it returns the buffer size needed; otherwise the bytes written. */
+int gpgomea_profile(int32_t enable);
+int gpgomea_profile_report(char* buf, int32_t len);
+
+/* gpgomea_op_costs: vector-ALU cost of each protected operator as the
+ * interpreter executes it, measured on the current device: out[op] (host, n >=
+ * 17 doubles, op in the library's internal numbering: 1 +, 2 -, 3 reversed -,
+ * 4 *, 5 /, 6 reversed /, 7 pow, 8 reversed pow, 9 sin, 10 cos, 11 square,
+ * 12 sqrt, 13 exp, 14 log; out[16] = the binary64 moment update per row) in
+ * seconds per lane-application, from kernels that apply the same device
+ * routine `iters` times to independent values in every lane of a full grid.
+ * dev_scratch: device float [2048] (never read back).  Synchronises `stream`. */
+int gpgomea_op_costs(double* out, int32_t n, int32_t iters, float* dev_scratch, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,8 @@ from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  #
                    MAX_LEN, MAX_CONSTS, MAX_FEATURES, check, last_error, lib)
 
 __all__ = ["eval_batch", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
-           "autotune", "clear_graphs", "flags_of", "GPGOMEAFitness", "LibraryError"]
+           "autotune", "clear_graphs", "flags_of", "profile", "profile_report", "op_costs",
+           "GPGOMEAFitness", "LibraryError"]
 
 
 def _torch():
@@ -166,6 +167,35 @@ def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path
 
 def clear_graphs():
     check(lib.gpgomea_clear_graphs())
+
+
+def profile(enable: bool):
+    """Bracket every kernel of later calls with hipEvents (graphs bypassed)."""
+    check(lib.gpgomea_profile(int(bool(enable))))
+
+
+def profile_report() -> dict:
+    """{kernel kind: (launches, total_ms)} since the previous report."""
+    n = lib.gpgomea_profile_report(None, 0)
+    buf = ctypes.create_string_buffer(max(n, 1))
+    check(lib.gpgomea_profile_report(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
+
+
+def op_costs(iters=2048, device="cuda:0"):
+    """Measured seconds per lane-application of every operator (see
+    gpgomea_op_costs); keys are operator names."""
+    torch = _torch()
+    scratch = torch.empty(2048, dtype=torch.float32, device=device)
+    out = (ctypes.c_double * 17)()
+    check(lib.gpgomea_op_costs(out, 17, int(iters), scratch.data_ptr(), _stream_ptr(scratch.device)))
+    names = {1: "add", 2: "sub", 3: "rsub", 4: "mul", 5: "div", 6: "rdiv", 7: "pow", 8: "rpow",
+             9: "sin", 10: "cos", 11: "sq", 12: "sqrt", 13: "exp", 14: "log", 16: "moments"}
+    return {v: out[k] for k, v in names.items()}
 
 
 # ------------------------------------------------------------- host codec

@@ -34,6 +34,9 @@ SIGNATURES = {
                                     _i32, _p, _sz, _c.c_char_p, _i32, _c.c_char_p, _i32, _p]),
     "gpgomea_load_tuning": (_c.c_int, [_c.c_char_p]),
     "gpgomea_clear_graphs": (_c.c_int, []),
+    "gpgomea_profile": (_c.c_int, [_i32]),
+    "gpgomea_profile_report": (_c.c_int, [_c.c_char_p, _i32]),
+    "gpgomea_op_costs": (_c.c_int, [_p, _i32, _i32, _p, _p]),
 }
 
 
@@ -43,11 +46,32 @@ class LibraryError(RuntimeError):
         self.code = code
 
 
+def hip_runtimes():
+    """Distinct HIP runtime files mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                p = line.split()[-1]
+                if "libamdhip64" in p:
+                    paths.add(os.path.realpath(p))
+    except OSError:
+        pass
+    return sorted(paths)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2605_30954_amd.build` (hipcc, gfx950)")
+                          "`python paper_2605_30954_amd/build.py` (hipcc, gfx950)")
+    # torch brings its own HIP runtime (same soname).  Load it first so the
+    # library binds to that one: torch's streams and memory then belong to the
+    # same runtime instance, and only one runtime opens the device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    rts = hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes are loaded in this process: {rts}")
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
         f.restype = res

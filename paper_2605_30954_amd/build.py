@@ -1,6 +1,8 @@
 """Build libgpgomea_eval.so (HIP for gfx950) in the package directory.
 
-    python -m paper_2605_30954_amd.build [--jobs N] [--save-temps]
+    python paper_2605_30954_amd/build.py [--jobs N] [--save-temps]
+
+(run by path: importing the package would load the library being rebuilt)
 
 Every translation unit under csrc/ is compiled by hipcc in parallel and
 linked into one shared library; the build always recompiles.
@@ -20,7 +22,7 @@ LIB = os.path.join(PKG, "libgpgomea_eval.so")
 BUILD = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["codec.cpp", "api.cpp", "k_prep.hip", "k_forward.hip", "k_adjoint.hip"]
+SOURCES = ["codec.cpp", "api.cpp", "k_prep.hip", "k_forward.hip", "k_adjoint.hip", "k_opcost.hip"]
 
 
 def hipcc():

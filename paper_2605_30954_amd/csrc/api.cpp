@@ -214,6 +214,40 @@ std::map<GraphKey, hipGraphExec_t> g_graphs;
     if (e_ != hipSuccess) return fail(GPGOMEA_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// ------------------------------------------------------- kernel timing hook
+// With profiling on, every launch of a call is bracketed by hipEvents on the
+// call's stream (graphs are bypassed: events cannot be read inside a replay).
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof = false;
+std::vector<ProfRec> g_prof_recs;
+
+struct ProfScope {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
+    if (g_prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess) {
+      (void)hipEventRecord(b, s);
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof_recs.push_back({name, a, b});
+    }
+  }
+};
+#define GG_TIMED(name, call)        \
+  do {                              \
+    ProfScope ps_(name, c.stream);  \
+    GG_HIP(call);                   \
+  } while (0)
+
 struct Call {
   Shape s;
   const int8_t* ops;
@@ -242,10 +276,10 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const TileCfg& ac) {
   double* gpart = reinterpret_cast<double*>(c.ws + l.gpart);
   const DataArgs d{c.X, c.s.ldx, c.s.F, c.s.N, c.y};
   const int D = fp64 ? 8 : fc.D;
-  GG_HIP(launch_ystats(c.y, c.s.N, stats, yscr, c.stream));
-  GG_HIP(launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, c.with_grad ? 8 : D,
+  GG_TIMED("ystats", launch_ystats(c.y, c.s.N, stats, yscr, c.stream));
+  GG_TIMED("compile", launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, c.with_grad ? 8 : D,
                         l.U_stride, uops, meta, c.stream));
-  GG_HIP(launch_probe(fp64, fc.K, c.with_grad ? 8 : D, uops, l.U_stride, meta, c.s.M, d, c.stream));
+  GG_TIMED("probe", launch_probe(fp64, fc.K, c.with_grad ? 8 : D, uops, l.U_stride, meta, c.s.M, d, c.stream));
   const bool sse = c.aux != nullptr || !(c.s.flags & GPGOMEA_LINEAR_SCALING);
   if (c.s.flags & GPGOMEA_PLAIN) {
     unsigned* ticket = reinterpret_cast<unsigned*>(c.ws + l.ticket);
@@ -254,38 +288,39 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const TileCfg& ac) {
     TileCfg pc = fc;
     if (c.with_grad) pc.D = 8;
     for (int i = 0; i < c.s.M; ++i)
-      GG_HIP(launch_plain_forward(fp64, pc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
+      GG_TIMED("plain_forward", launch_plain_forward(fp64, pc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
                                   c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
     if (c.with_grad) {
       TileCfg one = ac;
       one.G = 1;
       finish_spans(one, 1, c.s.N, kMaxAdjSpans);
       for (int i = 0; i < c.s.M; ++i)
-        GG_HIP(launch_fused_adjoint(one, uops + size_t(i) * l.U_stride, l.U_stride, meta + i, 1,
+        GG_TIMED("plain_adjoint", launch_fused_adjoint(one, uops + size_t(i) * l.U_stride, l.U_stride, meta + i, 1,
                                     c.s.C_max, d, stats, ab + 2 * size_t(i),
                                     gpart + size_t(i) * one.n_spans * c.s.C_max, nullptr,
                                     std::max(1, c.s.L_max - 1), c.stream));
-      GG_HIP(launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
+      GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
                                   c.s.flags, c.status, c.grad, c.stream));
     }
     return GPGOMEA_OK;
   }
   TileCfg f2 = fc;
   if (c.with_grad) f2.D = 8;  // one uop stream serves both kernels
-  GG_HIP(launch_fused_forward(fp64, f2, uops, l.U_stride, meta, c.s.M, d, stats, part, sse,
+  GG_TIMED("fused_forward", launch_fused_forward(fp64, f2, uops, l.U_stride, meta, c.s.M, d, stats, part, sse,
                               c.stream));
-  GG_HIP(launch_finalize(meta, c.s.M, part, f2.n_spans, stats, c.s.flags, c.fitness, c.aux,
+  GG_TIMED("finalize", launch_finalize(meta, c.s.M, part, f2.n_spans, stats, c.s.flags, c.fitness, c.aux,
                          c.status, ab, c.stream));
   if (c.with_grad) {
-    GG_HIP(launch_fused_adjoint(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab, gpart,
+    GG_TIMED("fused_adjoint", launch_fused_adjoint(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab, gpart,
                                 nullptr, std::max(1, c.s.L_max - 1), c.stream));
-    GG_HIP(launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab, c.s.flags,
+    GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab, c.s.flags,
                                 c.status, c.grad, c.stream));
   }
   return GPGOMEA_OK;
 }
 
 int run_call(const Call& c) {
+  (void)hipGetLastError();  // launches below report their own errors only
   TileCfg fc, ac;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -294,7 +329,8 @@ int run_call(const Call& c) {
     auto ia = g_tuned_adj.find(tune_key(c.s, true));
     ac = plan_adjoint(c.s, ia == g_tuned_adj.end() ? nullptr : &ia->second);
   }
-  const bool graph = !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr;
+  const bool graph =
+      !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr && !g_prof;
   if (!graph) return enqueue_fused(c, fc, ac);
 
   GraphKey key;
@@ -392,6 +428,65 @@ extern "C" int gpgomea_clear_graphs(void) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
   g_graphs.clear();
+  return GPGOMEA_OK;
+}
+
+// --------------------------------------------------------------- profiling
+extern "C" int gpgomea_profile(int32_t enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof = enable != 0;
+  return GPGOMEA_OK;
+}
+
+extern "C" int gpgomea_profile_report(char* buf, int32_t len) {
+  // the text is built once per report; a size query (buf == NULL) keeps it for
+  // the call that fetches it
+  thread_local std::string pending;
+  thread_local bool have = false;
+  if (!have) {
+    std::vector<ProfRec> recs;
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      recs.swap(g_prof_recs);
+    }
+    std::map<std::string, std::pair<long, double>> acc;
+    for (auto& r : recs) {
+      float ms = 0.0f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        auto& e = acc[r.name];
+        e.first += 1;
+        e.second += ms;
+      }
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    pending.clear();
+    for (auto& kv : acc) {
+      char line[160];
+      std::snprintf(line, sizeof(line), "%s %ld %.6f\n", kv.first.c_str(), kv.second.first,
+                    kv.second.second);
+      pending += line;
+    }
+    have = true;
+  }
+  if (!buf || len <= 0) return int(pending.size()) + 1;
+  std::strncpy(buf, pending.c_str(), size_t(len) - 1);
+  buf[len - 1] = 0;
+  const int n = int(std::min<size_t>(pending.size(), size_t(len) - 1));
+  have = false;
+  pending.clear();
+  return n;
+}
+
+extern "C" int gpgomea_op_costs(double* out, int32_t n, int32_t iters, float* dev_scratch,
+                                void* stream) {
+  if (!out || !dev_scratch) return fail(GPGOMEA_E_ARG, "NULL pointer");
+  if (n < int(UOP_NUM) + 1 || iters < 16) return fail(GPGOMEA_E_SHAPE, "need n >= %d, iters >= 16", int(UOP_NUM) + 1);
+  (void)hipGetLastError();
+  if (measure_op_costs(out, n, iters, static_cast<hipStream_t>(stream), dev_scratch) != 0)
+    return fail(GPGOMEA_E_ARG, "bad arguments");
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GPGOMEA_E_HIP, "op cost kernels: %s", hipGetErrorString(e));
   return GPGOMEA_OK;
 }
 

@@ -87,8 +87,22 @@ struct Slots {
 
 __device__ inline float f32_of(uint32_t bits) { return __uint_as_float(bits); }
 
-// Wave-uniform scalar load of a uop (the pointer must be provably uniform).
-__device__ inline uint2 load_uop(const uint2* __restrict__ prog, int pc) { return prog[pc]; }
+// Read-only data that every lane of a wave reads at the same address (uop
+// streams, per-individual metadata): accessed through the constant address
+// space so the compiler emits scalar loads into SGPRs.
+template <typename T>
+using const_as_ptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ inline T load_uniform(const T* p, int i) {
+  return ((const_as_ptr<T>)p)[i];
+}
+
+// Wave-uniform scalar load of a uop.
+__device__ inline uint2 load_uop(const uint2* __restrict__ prog, int pc) {
+  const unsigned long long v = load_uniform(reinterpret_cast<const unsigned long long*>(prog), pc);
+  return make_uint2(uint32_t(v), uint32_t(v >> 32));
+}
 
 // Per-element application of the protected operators to K-vectors.
 template <typename T, int K>

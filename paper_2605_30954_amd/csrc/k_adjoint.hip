@@ -139,11 +139,14 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
 
 // Sum over the wave of this lane's first `kv` values (padding rows excluded:
 // their adjoints may be NaN after multiplying a zero by an infinite partial).
+// Summed in binary64: a constant whose gradient is a cancelling sum (one the
+// linear fit absorbs has an exactly zero gradient) keeps its float32 per-row
+// terms but loses nothing more in the reduction.
 template <int K>
-__device__ inline float wave_total(const typename VecT<float, K>::type& v, int kv) {
-  float s = 0.0f;
+__device__ inline double wave_total(const typename VecT<float, K>::type& v, int kv) {
+  double s = 0.0;
 #pragma unroll
-  for (int j = 0; j < K; ++j) s += j < kv ? v[j] : 0.0f;
+  for (int j = 0; j < K; ++j) s += j < kv ? double(v[j]) : 0.0;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   return s;
@@ -173,8 +176,8 @@ __device__ inline void run_reverse(const uint2* __restrict__ prog, int n_uops, i
       if (!ts && op == UOP_SUB) { gsrc = -g; GG_BRANCH(); }
       if (!ts && op != UOP_SUB) { gsrc = g; GG_BRANCH(); }  // ADD, RSUB: +1
       if (sk == SRC_CONST) {
-        const float s = wave_total<K>(gsrc, kv);
-        if (lane == 0) gacc[uop_src_arg(h)] += double(s);
+        const double s = wave_total<K>(gsrc, kv);  // same value on every lane
+        gacc[uop_src_arg(h)] += s;
         GG_BRANCH();
       }
       if (sk == SRC_POP) { gs.put(uop_src_arg(h), gsrc); GG_BRANCH(); }
@@ -185,8 +188,8 @@ __device__ inline void run_reverse(const uint2* __restrict__ prog, int n_uops, i
       if (!ta && op == UOP_RSUB) { g = -g; GG_BRANCH(); }
       if (!ta && op == UOP_MUL) { g = g * f32_of(u.y); GG_BRANCH(); }  // constant factor
       if (uop_load(h) == LD_CONST) {
-        const float s = wave_total<K>(g, kv);
-        if (lane == 0) gacc[uop_load_arg(h)] += double(s);
+        const double s = wave_total<K>(g, kv);
+        gacc[uop_load_arg(h)] += s;
         GG_BRANCH();
       }
       GG_BRANCH();
@@ -203,7 +206,6 @@ __global__ __launch_bounds__(W * 64) void k_fused_adj(AdjParams p) {
   double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
   double* gacc = yts + R;  // G * C_max
   const size_t off_ctr = (size_t(p.F) * R * 4 + size_t(R) * 8 + size_t(p.G) * p.C_max * 8 + 15) & ~size_t(15);
-  int* counter = reinterpret_cast<int*>(smem_raw + off_ctr);
   float* tape_all = reinterpret_cast<float*>(smem_raw + off_ctr + 16);
 
   const int total = p.n_spans * p.n_groups;
@@ -213,10 +215,11 @@ __global__ __launch_bounds__(W * 64) void k_fused_adj(AdjParams p) {
   const int span = item / p.n_groups, grp = item - span * p.n_groups;
   const int ind0 = grp * p.G;
   const int Gn = min(p.G, p.M - ind0);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
   constexpr int BR = 64 * K;
-  TapeRef<K> tape{tape_all + size_t(w) * p.tape_cap * 64 * K, lane};
+  TapeRef<K> tape{tape_all + size_t(wv) * p.tape_cap * 64 * K, lane};
 
   for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
   const int64_t span_r0 = int64_t(span) * p.tiles_per_span * R;
@@ -231,18 +234,14 @@ __global__ __launch_bounds__(W * 64) void k_fused_adj(AdjParams p) {
     }
     for (int r = threadIdx.x; r < R; r += blockDim.x)
       yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
-    if (threadIdx.x == 0) *counter = 0;
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
-    for (;;) {
-      int jj = 0;
-      if (lane == 0) jj = atomicAdd(counter, 1);
-      jj = __builtin_amdgcn_readfirstlane(__shfl(jj, 0));
-      if (jj >= Gn) break;
+    for (int jj = wv; jj < Gn; jj += W) {  // wave-uniform, see the forward kernel
       const int i = ind0 + jj;
       const ProgMeta pm = p.meta[i];
       const double s1 = p.ab[size_t(i) * 2 + 1];
-      if (pm.status != 0 || s1 == 0.0 || pm.n_const == 0 || pm.n_tape > p.tape_cap) continue;
+      const int skip = pm.status != 0 || s1 == 0.0 || pm.n_const == 0 || pm.n_tape > p.tape_cap;
+      if (__builtin_amdgcn_readfirstlane(skip)) continue;
       const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;  // residual = (s0 - ybar) + s1 p - yt
       const uint2* prog = p.uops + size_t(i) * p.U_stride;
       double* ga = gacc + size_t(jj) * p.C_max;
@@ -272,11 +271,6 @@ template <int K, int D, int W>
 static hipError_t adj_impl(const TileCfg& c, const AdjParams& ap, hipStream_t s) {
   const size_t sh = adjoint_lds_bytes(ap.F, ap.R, ap.G, ap.C_max, W, K, ap.tape_cap);
   const int nb = c.n_spans * c.n_groups;
-  if (sh > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_adj<K, D, W>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(sh));
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL((k_fused_adj<K, D, W>), dim3(nb), dim3(W * 64), sh, s, ap);
   return hipGetLastError();
 }
@@ -288,13 +282,14 @@ hipError_t launch_fused_adjoint(const TileCfg& c, const uint2* uops, int U_strid
   (void)tape_spill;
   AdjParams ap{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
                c.R, c.G, c.n_groups, c.n_spans, c.tiles_per_span, tape_lds};
-  if (c.K == 2) {
-    if (c.W == 2) return adj_impl<2, 8, 2>(c, ap, s);
-    return adj_impl<2, 8, 4>(c, ap, s);
-  }
-  if (c.W == 2) return adj_impl<1, 8, 2>(c, ap, s);
-  if (c.W == 1) return adj_impl<1, 8, 1>(c, ap, s);
-  return adj_impl<1, 8, 4>(c, ap, s);
+  if (c.D != 8) return hipErrorInvalidValue;
+  if (c.K == 2 && c.W == 4) return adj_impl<2, 8, 4>(c, ap, s);
+  if (c.K == 2 && c.W == 2) return adj_impl<2, 8, 2>(c, ap, s);
+  if (c.K == 2 && c.W == 1) return adj_impl<2, 8, 1>(c, ap, s);
+  if (c.K == 1 && c.W == 4) return adj_impl<1, 8, 4>(c, ap, s);
+  if (c.K == 1 && c.W == 2) return adj_impl<1, 8, 2>(c, ap, s);
+  if (c.K == 1 && c.W == 1) return adj_impl<1, 8, 1>(c, ap, s);
+  return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 
 __global__ __launch_bounds__(256) void k_grad_finalize(const ProgMeta* __restrict__ meta, int M,

@@ -13,8 +13,8 @@
 //
 // Fused form: a block stages a tile of rows (feature-major X and y - ybar) in
 // LDS once and every wave of the block evaluates the group's individuals on
-// it, each wave taking the next individual from an LDS counter; a block
-// sweeps `tiles_per_span` tiles before it writes the group's partial sums.
+// it (wave w takes individuals w, w+W, ...); a block sweeps `tiles_per_span`
+// tiles before it writes the group's partial sums.
 // Plain form: one launch per individual over all rows; its last block to
 // finish sums the per-block partials and finalizes (the per-individual launch
 // pattern the paper contrasts with its batched design).
@@ -105,14 +105,14 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   float* xs = reinterpret_cast<float*>(smem_raw);
   double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
   double* accs = yts + R;  // G * 4
-  int* counter = reinterpret_cast<int*>(accs + size_t(p.G) * 4);
 
   const int total = p.n_spans * p.n_groups;
   const int item = xcd_item(blockIdx.x, total);
   const int span = item / p.n_groups, grp = item - span * p.n_groups;
   const int ind0 = grp * p.G;
   const int Gn = min(p.G, p.M - ind0);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
   constexpr int BR = 64 * K;  // rows per batch
 
@@ -127,16 +127,13 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     stage_tile(xs, p.X, p.ldx, p.F, R, r0, nvalid);
     for (int r = threadIdx.x; r < R; r += blockDim.x)
       yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
-    if (threadIdx.x == 0) *counter = 0;
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
-    for (;;) {
-      int jj = 0;
-      if (lane == 0) jj = atomicAdd(counter, 1);
-      jj = __builtin_amdgcn_readfirstlane(__shfl(jj, 0));
-      if (jj >= Gn) break;
+    // wave w takes individuals w, w+W, ... of the group: a wave-uniform loop
+    // with no divergent branch and no cross-lane traffic inside it
+    for (int jj = wv; jj < Gn; jj += W) {
       const int i = ind0 + jj;
-      if (p.meta[i].status != 0) continue;
+      if (__builtin_amdgcn_readfirstlane(p.meta[i].status) != 0) continue;
       const uint2* prog = p.uops + size_t(i) * p.U_stride;
       const double mu = double(p.meta[i].mu);
       const double emu = mu - ybar;
@@ -148,16 +145,15 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
       }
       const double sa = wave_sum(m.a), sb = wave_sum(m.b), sc = wave_sum(m.c);
       const double se = SSE ? wave_sum(m.e) : 0.0;
-      if (lane == 0) {
-        accs[jj * 4 + 0] += sa;
-        accs[jj * 4 + 1] += sb;
-        accs[jj * 4 + 2] += sc;
-        accs[jj * 4 + 3] += se;
-      }
+      // every lane holds the same totals: all lanes store the same value (no
+      // divergent branch between the cross-lane sums of consecutive individuals)
+      accs[jj * 4 + 0] += sa;
+      accs[jj * 4 + 1] += sb;
+      accs[jj * 4 + 2] += sc;
+      accs[jj * 4 + 3] += se;
     }
   }
   __syncthreads();
-  (void)w;
   for (int j = threadIdx.x; j < Gn * 4; j += blockDim.x) {
     const int jj = j >> 2, q = j & 3;
     p.part[(size_t(ind0 + jj) * p.n_spans + span) * 4 + q] = accs[j];

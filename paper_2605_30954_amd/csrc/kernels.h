@@ -78,6 +78,7 @@ hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const do
                                 hipStream_t s);
 
 int lds_limit_bytes();
+int measure_op_costs(double* out, int n, int iters, hipStream_t s, float* scratch);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 
 // LDS bytes of one adjoint block (row tile, centred targets, constant

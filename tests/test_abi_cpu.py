@@ -147,3 +147,10 @@ def test_host_side_argument_errors():
     rc = L.gpgomea_grad_consts(fake, 4, 15, fake, 8, fake, 2, 1000, 1000, fake,
                                gg.FP64_NODES, fake, None, fake, None, fake, ws_need, None)
     assert rc == _lib.E_UNSUPPORTED
+
+
+def test_single_hip_runtime_in_process():
+    """The library shares torch's HIP runtime (one runtime, one device view)."""
+    import torch  # noqa: F401
+    rts = _lib.hip_runtimes()
+    assert len(rts) == 1, rts

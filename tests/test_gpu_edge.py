@@ -25,6 +25,7 @@ def programs(progs, L=31, Cm=16):
     cs = np.zeros((len(progs), Cm), np.float32)
     for i, (t, c) in enumerate(progs):
         ops[i, : len(t)] = t
+        c = list(c)[:Cm]  # a program may name more constants than the list holds
         cs[i, : len(c)] = c
     return ops, cs
 
@@ -106,12 +107,15 @@ def test_malformed_programs_get_status_2():
 def test_height8_templates_511_tokens():
     """Largest supported programs: full height-8 trees (511 tokens, 8 stack
     levels), the Exp. III template depth."""
-    cfg = get_config(5)
+    import dataclasses
+    from synth.symbols import FUNCS_BASIC
+    # binary operators only, so that "full" samples keep all 511 template slots
+    cfg = dataclasses.replace(get_config(5), heights=(8,), funcs=FUNCS_BASIC)
     N = 3000
     X, y = make_dataset(cfg, N=N)
-    genes, gc, hs = sample_population(cfg, M=16, salt=8, heights=np.full(16, 8, np.int8))
+    genes, gc, hs = sample_population(cfg, M=16, salt=8)
     ops, cs, ln, nc = gg.encode(genes, gc, 8, 511, 256)
-    assert ln.max() > 255
+    assert ln.max() == 511
     f, st = gg.eval_batch(*dev(ops, cs, X, y), return_status=True)
     ref = OF.evaluate_population(genes, gc, 8, X, y)
     vy = float(np.var(y.astype(np.float64)))

@@ -13,7 +13,8 @@ from synth import get_config
 pytestmark = pytest.mark.gpu
 
 
-def run_grad(cid, M, N, linear_scaling=True, plain=False, salt=1):
+def run_grad(cid, M, N, linear_scaling=True, plain=False, salt=1, min_gated=None):
+    min_gated = M // 3 if min_gated is None else min_gated
     cfg = get_config(cid)
     log(f"[case] grad cfg{cid} M={M} N={N} ls={linear_scaling} plain={plain}")
     d = make_inputs(cfg, M, N, salt)
@@ -28,7 +29,9 @@ def run_grad(cid, M, N, linear_scaling=True, plain=False, salt=1):
     gate_fitness(fit, st, ref, fl, vy, "f32", f"grad-call fitness cfg{cid}")
     refs = oracle_gradients(d, idx, linear_scaling)
     rep = gate_gradients(grad, st, refs, fl, vy, what=f"cfg{cid} ls={linear_scaling} plain={plain}")
-    assert rep["gated"] >= M // 3
+    assert rep["gated"] >= min_gated
+    # individuals too ill-conditioned for the gate still get a finite gradient
+    assert np.all(np.isfinite(grad[st == 0]))
     return d, grad, st, refs, fl, vy
 
 
@@ -45,7 +48,10 @@ def test_cfg2_gradients():
 
 
 def test_cfg5_gradients_full_operator_set():
-    run_grad(5, 24, 3001)
+    # most random height-7 programs over all 11 operators have gradients that a
+    # one-ulp perturbation of the node values moves by more than the gate: they
+    # are flagged, so a larger sample keeps enough gateable individuals
+    run_grad(5, 64, 3001, min_gated=10)
 
 
 def test_plain_adjoint_matches_fused():
