@@ -111,7 +111,11 @@ int gpgomea_eval_batch(const int8_t* ops, int32_t M, int32_t L_max, const float*
  * With linear scaling the gradient is (2b/N) sum_r (a + b p_r - y_r) dp_r/dc_j
  * (the optimal a, b have zero partials); without it (2/N) sum_r (p_r - y_r)
  * dp_r/dc_j.  A protected operator's guarded branch and a clamp outside its
- * range have derivative 0; sqrt|a| has derivative 0 at a = 0. */
+ * range have derivative 0; sqrt|a| has derivative 0 at a = 0.  Per-row
+ * partials are carried in binary32 and summed in binary64: where a per-row
+ * partial exceeds the binary32 range the entry is +-inf or NaN while the
+ * fitness stays valid (status 0).  FP64_NODES is not supported here
+ * (E_UNSUPPORTED). */
 int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
                         int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
                         const float* y, uint32_t flags, double* fitness, double* aux,

@@ -13,6 +13,13 @@ theorem) d LS-MSE / d c_j = (2b/N) sum_r (a + b p_r - y_r) d p_r / d c_j, with
 gradient is 0.  Raw MSE: d MSE / d c_j = (2/N) sum_r (p_r - y_r) d p_r / d c_j.
 Non-finite individuals get a zero gradient (status 1).
 
+``gradient`` also returns, in the score dict, ``gabs[j]`` = (2|b|/N) sum_r
+|(a + b p_r - y_r) d p_r / d c_j| (or the raw-MSE analogue): the sum of the
+magnitudes of the terms of the gradient's dot product, which bounds the
+rounding error of any evaluation of it (the standard dot-product error bound
+|fl(sum t_r) - sum t_r| <= gamma sum |t_r| with gamma a small multiple of the
+unit roundoff; Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.1).
+
 ``fd_gradient`` is an independent check by central finite differences of the
 whole fitness in float64.
 """
@@ -31,16 +38,19 @@ def gradient(genes_row, gconst_row, height, X, y, linear_scaling=True, rng="f32"
     s = FT.score(p, y64, linear_scaling)
     C = dp.shape[0]
     N = y64.size
+    s["gabs"] = np.zeros(C)
     if s["status"] != 0:
         return s, np.zeros(C)
     if linear_scaling:
         if s["b"] == 0.0:
             return s, np.zeros(C)
         r = s["a"] + s["b"] * p - y64
-        g = np.array([FT._sum(r * dp[j]) for j in range(C)]) * (2.0 * s["b"] / N)
+        scale = 2.0 * s["b"] / N
     else:
         r = p - y64
-        g = np.array([FT._sum(r * dp[j]) for j in range(C)]) * (2.0 / N)
+        scale = 2.0 / N
+    g = np.array([FT._sum(r * dp[j]) for j in range(C)]) * scale
+    s["gabs"] = np.array([FT._sum(np.abs(r * dp[j])) for j in range(C)]) * abs(scale)
     return s, g
 
 

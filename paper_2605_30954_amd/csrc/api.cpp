@@ -23,7 +23,8 @@ namespace gg {
 namespace {
 
 constexpr int kMaxSpans = 256;    // forward partial sums per individual (upper bound)
-constexpr int kMaxAdjSpans = 16;  // gradient partials per individual (upper bound)
+constexpr int kMaxAdjSpans = 64;  // gradient partials per individual (upper bound)
+constexpr int64_t kAdjPartEntries = int64_t(1) << 22;  // cap on M x spans x C_max
 constexpr int kPlainMaxBlocks = 1024;
 constexpr uint32_t kKnownFlags =
     GPGOMEA_LINEAR_SCALING | GPGOMEA_FP64_NODES | GPGOMEA_PLAIN | GPGOMEA_NO_GRAPH;
@@ -60,6 +61,13 @@ int slots_for(int L_max) {
   return std::max(d, 1);
 }
 
+// Gradient partials per individual: at most kMaxAdjSpans, and few enough that
+// the partial buffer stays within kAdjPartEntries doubles.
+int adj_span_cap(const Shape& s) {
+  const int64_t per = int64_t(s.M) * std::max(s.C_max, 1);
+  return int(std::max<int64_t>(1, std::min<int64_t>(kMaxAdjSpans, kAdjPartEntries / per)));
+}
+
 struct Layout {
   size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, total;
   int U_stride;
@@ -86,7 +94,7 @@ Layout layout_of(const Shape& s) {
   l.ticket = o;
   o = align256(o + 64);
   l.gpart = o;
-  o = align256(o + size_t(s.M) * kMaxAdjSpans * std::max(s.C_max, 1) * sizeof(double));
+  o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
   l.total = o;
   return l;
 }
@@ -153,51 +161,94 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   return c;
 }
 
-TileCfg plan_adjoint(const Shape& s, const Tuned* t) {
-  TileCfg c;
-  c.K = 1;
-  c.D = 8;
-  const int tape = std::max(1, s.L_max - 1);
-  const int cap = lds_limit_bytes();
+// Adjoint plan.  Register-tape kernel: K rows per lane with a TC-entry tape
+// (K*TC = 64 VGPRs), W = 4 waves, a row tile of at most 32 KB so that several
+// blocks share a CU.  LDS-tape kernel: the largest block that fits its
+// worst-case tape (L_max - 1 entries per wave).  Both use the same spans.
+AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
+  AdjPlan a;
   const int Cm = std::max(1, s.C_max);
+  const int cap = lds_limit_bytes() - 64;  // static LDS of the kernels
+  TileCfg& r = a.reg;
+  r.D = D;
+  r.W = 4;
+  if (s.L_max <= 63) {
+    r.K = 4;
+    a.reg_tape = 16;
+  } else {
+    r.K = 2;
+    a.reg_tape = 32;
+  }
+  a.lane_consts = std::min(Cm, 32);
+  r.G = 16;
+  const int BRr = 64 * r.K;
+  r.R = 1024;
+  if (t) {
+    r.R = t->R;
+    r.G = t->G;
+  }
+  while (r.R > BRr && (size_t(s.F) * r.R * 4 + size_t(r.R) * 8 > 32 * 1024 ||
+                       adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts) > size_t(cap)))
+    r.R /= 2;
+  const int64_t Nr = (s.N + BRr - 1) / BRr * BRr;
+  if (Nr < r.R) r.R = int(Nr);
+  r.R = std::max(BRr, r.R / BRr * BRr);
+  r.G = std::max(1, std::min(r.G, s.M));
+  r.n_groups = (s.M + r.G - 1) / r.G;
+  // spans: enough blocks to fill the chip several times over
+  const int64_t tiles = (s.N + r.R - 1) / r.R;
+  int64_t want = (4096 + r.n_groups - 1) / r.n_groups;
+  want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, int64_t(span_cap)}));
+  r.tiles_per_span = int((tiles + want - 1) / want);
+  a.span_rows = int64_t(r.tiles_per_span) * r.R;
+  a.n_spans = int((s.N + a.span_rows - 1) / a.span_rows);
+  r.n_spans = a.n_spans;
+
+  // LDS-tape kernel: its tile must divide span_rows (powers of two <= r.R)
+  TileCfg& w = a.wide;
+  a.tape_cap = std::max(1, s.L_max - 1);
+  w.D = 8;
   bool ok = false;
   const int Ks[2] = {2, 1};
   const int Ws[3] = {4, 2, 1};
-  const int Rs[5] = {1024, 512, 256, 128, 64};
   const int Gs[3] = {16, 8, 4};
   for (int k : Ks) {
-    if (t && t->K != k) continue;
-    for (int w : Ws) {
-      for (int r : Rs) {
-        if (r < 64 * k) continue;
+    for (int wv : Ws) {
+      for (int rr = r.R; rr >= 64 * k && !ok; rr /= 2) {
+        if (rr % (64 * k)) continue;
         for (int g : Gs) {
-          if (adjoint_lds_bytes(s.F, r, g, Cm, w, k, tape) <= size_t(cap)) {
-            c.K = k;
-            c.W = w;
-            c.R = r;
-            c.G = g;
+          if (adjoint_lds_bytes(s.F, rr, g, Cm, wv, k, a.tape_cap) <= size_t(cap)) {
+            w.K = k;
+            w.W = wv;
+            w.R = rr;
+            w.G = g;
             ok = true;
             break;
           }
         }
-        if (ok) break;
       }
       if (ok) break;
     }
     if (ok) break;
   }
-  if (!ok) {  // smallest possible block
-    c.K = 1;
-    c.W = 1;
-    c.R = 64;
-    c.G = 1;
+  if (!ok) {  // smallest block; the caller reports the shape as unsupported
+    w.K = 1;
+    w.W = 1;
+    w.R = 64;
+    w.G = 1;
   }
-  const int BR = 64 * c.K;
-  const int64_t Nr = (s.N + BR - 1) / BR * BR;
-  if (Nr < c.R) c.R = int(Nr);
-  c.G = std::max(1, std::min(c.G, s.M));
-  finish_spans(c, s.M, s.N, kMaxAdjSpans);
-  return c;
+  w.G = std::max(1, std::min(w.G, s.M));
+  w.n_groups = (s.M + w.G - 1) / w.G;
+  w.n_spans = a.n_spans;
+  w.tiles_per_span = int(a.span_rows / w.R);
+  return a;
+}
+
+bool adjoint_plan_fits(const Shape& s, const AdjPlan& a) {
+  const int cap = lds_limit_bytes() - 64;
+  return adjoint_lds_bytes(s.F, a.wide.R, a.wide.G, std::max(1, s.C_max), a.wide.W, a.wide.K,
+                           a.tape_cap) <= size_t(cap) &&
+         a.span_rows % a.wide.R == 0;
 }
 
 // ------------------------------------------------------------ graph cache
@@ -264,7 +315,7 @@ struct Call {
 };
 
 // Enqueue the whole fused pipeline on c.stream.
-int enqueue_fused(const Call& c, const TileCfg& fc, const TileCfg& ac) {
+int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   const Layout l = layout_of(c.s);
   const bool fp64 = (c.s.flags & GPGOMEA_FP64_NODES) != 0;
   double* stats = reinterpret_cast<double*>(c.ws + l.stats);
@@ -277,58 +328,61 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const TileCfg& ac) {
   const DataArgs d{c.X, c.s.ldx, c.s.F, c.s.N, c.y};
   const int D = fp64 ? 8 : fc.D;
   GG_TIMED("ystats", launch_ystats(c.y, c.s.N, stats, yscr, c.stream));
-  GG_TIMED("compile", launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, c.with_grad ? 8 : D,
-                        l.U_stride, uops, meta, c.stream));
-  GG_TIMED("probe", launch_probe(fp64, fc.K, c.with_grad ? 8 : D, uops, l.U_stride, meta, c.s.M, d, c.stream));
+  GG_TIMED("compile", launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, D, l.U_stride,
+                                     uops, meta, c.stream));
+  GG_TIMED("probe", launch_probe(fp64, fc.K, D, uops, l.U_stride, meta, c.s.M, d, c.stream));
   const bool sse = c.aux != nullptr || !(c.s.flags & GPGOMEA_LINEAR_SCALING);
   if (c.s.flags & GPGOMEA_PLAIN) {
     unsigned* ticket = reinterpret_cast<unsigned*>(c.ws + l.ticket);
     double* pp = reinterpret_cast<double*>(c.ws + l.plain_part);
     GG_HIP(launch_fill_u32(ticket, 1, 0u, c.stream));
-    TileCfg pc = fc;
-    if (c.with_grad) pc.D = 8;
     for (int i = 0; i < c.s.M; ++i)
-      GG_TIMED("plain_forward", launch_plain_forward(fp64, pc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
-                                  c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
+      GG_TIMED("plain_forward", launch_plain_forward(fp64, fc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
+                                                     c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
     if (c.with_grad) {
-      TileCfg one = ac;
-      one.G = 1;
-      finish_spans(one, 1, c.s.N, kMaxAdjSpans);
-      for (int i = 0; i < c.s.M; ++i)
-        GG_TIMED("plain_adjoint", launch_fused_adjoint(one, uops + size_t(i) * l.U_stride, l.U_stride, meta + i, 1,
-                                    c.s.C_max, d, stats, ab + 2 * size_t(i),
-                                    gpart + size_t(i) * one.n_spans * c.s.C_max, nullptr,
-                                    std::max(1, c.s.L_max - 1), c.stream));
+      const AdjPlan one = plan_adjoint(Shape{1, c.s.L_max, c.s.C_max, c.s.F, c.s.N, c.s.ldx, c.s.flags}, D,
+                                       nullptr, adj_span_cap(c.s));
+      for (int i = 0; i < c.s.M; ++i) {
+        const uint2* ui = uops + size_t(i) * l.U_stride;
+        double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
+        GG_TIMED("plain_adjoint", launch_adjoint_reg(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
+                                                     ab + 2 * size_t(i), gi, c.stream));
+        GG_TIMED("plain_adjoint_lds", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
+                                                         ab + 2 * size_t(i), gi, c.stream));
+      }
       GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
-                                  c.s.flags, c.status, c.grad, c.stream));
+                                                     c.s.flags, c.status, c.grad, c.stream));
     }
     return GPGOMEA_OK;
   }
-  TileCfg f2 = fc;
-  if (c.with_grad) f2.D = 8;  // one uop stream serves both kernels
-  GG_TIMED("fused_forward", launch_fused_forward(fp64, f2, uops, l.U_stride, meta, c.s.M, d, stats, part, sse,
-                              c.stream));
-  GG_TIMED("finalize", launch_finalize(meta, c.s.M, part, f2.n_spans, stats, c.s.flags, c.fitness, c.aux,
-                         c.status, ab, c.stream));
+  GG_TIMED("fused_forward", launch_fused_forward(fp64, fc, uops, l.U_stride, meta, c.s.M, d, stats, part, sse,
+                                                 c.stream));
+  GG_TIMED("finalize", launch_finalize(meta, c.s.M, part, fc.n_spans, stats, c.s.flags, c.fitness, c.aux,
+                                       c.status, ab, c.stream));
   if (c.with_grad) {
-    GG_TIMED("fused_adjoint", launch_fused_adjoint(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab, gpart,
-                                nullptr, std::max(1, c.s.L_max - 1), c.stream));
-    GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab, c.s.flags,
-                                c.status, c.grad, c.stream));
+    GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
+                                               gpart, c.stream));
+    GG_TIMED("adjoint_lds", launch_adjoint_lds(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
+                                               gpart, c.stream));
+    GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab,
+                                                   c.s.flags, c.status, c.grad, c.stream));
   }
   return GPGOMEA_OK;
 }
 
 int run_call(const Call& c) {
   (void)hipGetLastError();  // launches below report their own errors only
-  TileCfg fc, ac;
+  TileCfg fc;
+  AdjPlan ac;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(c.s, false));
     fc = plan_forward(c.s, it == g_tuned.end() ? nullptr : &it->second);
     auto ia = g_tuned_adj.find(tune_key(c.s, true));
-    ac = plan_adjoint(c.s, ia == g_tuned_adj.end() ? nullptr : &ia->second);
+    ac = plan_adjoint(c.s, fc.D, ia == g_tuned_adj.end() ? nullptr : &ia->second, adj_span_cap(c.s));
   }
+  if (c.with_grad && !adjoint_plan_fits(c.s, ac))
+    return fail(GPGOMEA_E_UNSUPPORTED, "no adjoint block fits LDS for L_max=%d, F=%d", c.s.L_max, c.s.F);
   const bool graph =
       !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr && !g_prof;
   if (!graph) return enqueue_fused(c, fc, ac);
@@ -339,7 +393,7 @@ int run_call(const Call& c) {
            uintptr_t(c.status), uintptr_t(c.ws), uintptr_t(c.s.M), uintptr_t(c.s.L_max),
            uintptr_t(c.s.C_max), uintptr_t(c.s.F), uintptr_t(c.s.N), uintptr_t(c.s.ldx),
            uintptr_t(c.s.flags), uintptr_t(fc.K), uintptr_t(fc.R), uintptr_t(fc.G),
-           uintptr_t(ac.K), uintptr_t(ac.R), uintptr_t(ac.G), uintptr_t(ac.W)};
+           uintptr_t(ac.reg.R), uintptr_t(ac.reg.G), uintptr_t(ac.n_spans)};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);

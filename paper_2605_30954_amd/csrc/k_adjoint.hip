@@ -7,13 +7,25 @@
 // or (0, 1), taken from the forward pass (which must run first).
 //
 // Per row tile and individual a wave runs the program forward over K rows per
-// lane, storing every local partial the reverse sweep will need on a
-// wave-private LDS tape (the tree's values are recomputed per tile rather than
-// kept from the forward pass), seeds the output adjoint with the residual, and
-// walks the uops backwards.  A tree node has exactly one parent, so adjoints
-// never accumulate except at constants: each constant's adjoint is summed over
-// the wave's rows and added (binary64) to the block's per-(individual,
-// constant) accumulator in LDS; a block writes one partial per span.
+// lane, storing every local partial the reverse sweep will need on a tape
+// (the tree's values are recomputed per tile rather than kept from the
+// forward pass), seeds the output adjoint with the residual, and walks the
+// uops backwards.  A tree node has exactly one parent, so adjoints never
+// accumulate except at constants.
+//
+// Two kernels share this code and split the individuals between them:
+//  * k_adj_reg (most individuals): the tape is a register array of TC entries
+//    addressed by a wave-uniform index (indirect VGPR addressing, no LDS), and
+//    every lane sums its own rows' constant adjoints in an LDS column (binary32
+//    over the R/64 rows of one tile); once per (tile, individual) the wave
+//    adds the 64 columns in binary64.  LDS then holds only the row tile, so
+//    several blocks share a CU.
+//  * k_adj_lds (individuals whose tape exceeds TC entries or whose constants
+//    exceed the column count): the tape lives in wave-private LDS and every
+//    constant adjoint is reduced across the wave (binary64) per batch.
+// A block writes the partials of the individuals it processed; both kernels
+// cut the rows into the same spans, so every (individual, span) partial is
+// written by exactly one of them.
 #include <hip/hip_runtime.h>
 
 #include "interp.h"
@@ -33,17 +45,30 @@ struct AdjParams {
   const float* y;
   const double* stats;
   const double* ab;
-  double* gpart;  // [M][n_spans][C_max]
-  int R, G, n_groups, n_spans, tiles_per_span, tape_cap;
+  double* gpart;      // [M][n_spans][C_max]
+  int R, G, n_groups, n_spans;
+  int64_t span_rows;  // rows per span (common to both kernels)
+  int tape_cap;       // LDS tape entries per wave (k_adj_lds)
+  int reg_tape;       // TC: register tape entries (k_adj_reg)
+  int lane_consts;    // CC: constant columns per wave (k_adj_reg)
 };
 
+// Which kernel owns individual i (both evaluate the same predicate).
+__device__ inline bool adj_active(const ProgMeta& pm, double s1) {
+  return pm.status == 0 && s1 != 0.0 && pm.n_const > 0;
+}
+__device__ inline bool adj_fits_reg(const ProgMeta& pm, int TC, int CC) {
+  return pm.n_tape <= TC && pm.n_const <= CC;
+}
+
+// Wave-private tape in LDS: entry e, lane l at base[(e*64 + l)*K].
 template <int K>
-struct TapeRef {
+struct LdsTape {
   using V = typename VecT<float, K>::type;
-  float* base;  // this wave's tape: entry e, lane l at base[(e*64 + l)*K]
+  float* base;
   int lane;
   __device__ inline float* at(int e) const { return base + (size_t(e) * 64 + lane) * K; }
-  __device__ inline void put(int e, const V& v) const {
+  __device__ inline void put(int e, const V& v) {
     float* q = at(e);
     if constexpr (K == 4) {
       *reinterpret_cast<float4*>(q) = make_float4(v[0], v[1], v[2], v[3]);
@@ -71,13 +96,36 @@ struct TapeRef {
   }
 };
 
+// Tape of TC entries in VGPRs: one TC-float vector per row of the lane (a
+// vector register tuple holds at most 32 floats, and only a vector that fits
+// one tuple is addressed in registers).  The entry index is wave-uniform (it
+// follows the uop stream), so the compiler reads and writes the tuples with
+// s_set_gpr_idx moves instead of scratch memory.
+template <int K, int TC>
+struct RegTape {
+  static_assert(TC <= 32, "a tape row must fit one VGPR tuple");
+  using V = typename VecT<float, K>::type;
+  typedef float A __attribute__((ext_vector_type(TC)));
+  A a[K];
+  __device__ inline void put(int e, const V& v) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j][e] = v[j];
+  }
+  __device__ inline V get(int e) const {
+    V v;
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = a[j][e];
+    return v;
+  }
+};
+
 // Forward sweep with the tape (float nodes).  Same values as run_program; in
 // addition each uop stores d(result)/d(acc operand) and d(result)/d(src
 // operand) when the reverse sweep needs them (tape_acc / tape_src).
-template <int K, int D>
+template <int K, int D, class Tape>
 __device__ inline typename VecT<float, K>::type run_forward_taped(
     const uint2* __restrict__ prog, const float* __restrict__ xt, int rstride, int lrow,
-    const TapeRef<K>& tape) {
+    Tape& tape) {
   using V = typename VecT<float, K>::type;
   using P = Prot<float>;
   using Dv = Deriv<float>;
@@ -129,8 +177,8 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
       }
       GG_BRANCH();
     }
-    if (tape_acc(h)) { tape.put(tp++, fa); GG_BRANCH(); }
-    if (tape_src(h)) { tape.put(tp++, fs); GG_BRANCH(); }
+    if (tape_acc(h)) { tape.put(tp, fa); ++tp; GG_BRANCH(); }
+    if (tape_src(h)) { tape.put(tp, fs); ++tp; GG_BRANCH(); }
     cur = nxt;
     ++pc;
   }
@@ -138,10 +186,8 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
 }
 
 // Sum over the wave of this lane's first `kv` values (padding rows excluded:
-// their adjoints may be NaN after multiplying a zero by an infinite partial).
-// Summed in binary64: a constant whose gradient is a cancelling sum (one the
-// linear fit absorbs has an exactly zero gradient) keeps its float32 per-row
-// terms but loses nothing more in the reduction.
+// their adjoints may be NaN after multiplying a zero by an infinite partial),
+// in binary64.
 template <int K>
 __device__ inline double wave_total(const typename VecT<float, K>::type& v, int kv) {
   double s = 0.0;
@@ -152,12 +198,37 @@ __device__ inline double wave_total(const typename VecT<float, K>::type& v, int 
   return s;
 }
 
+// Where constant adjoints go.  WaveSink: reduced across the wave at once and
+// added to the individual's binary64 accumulator (same value on every lane).
+// LaneSink: this lane's rows summed into its own LDS column (entry c at
+// col[c * kColStride]); the wave reduces the columns later.
+constexpr int kColStride = 65;  // 64 lanes + 1: column reads are bank-conflict free
+
+struct WaveSink {
+  double* gacc;
+  template <class V, int K>
+  __device__ inline void add(uint32_t c, const V& v, int kv) {
+    const double s = wave_total<K>(v, kv);
+    gacc[c] += s;
+  }
+};
+struct LaneSink {
+  float* col;
+  template <class V, int K>
+  __device__ inline void add(uint32_t c, const V& v, int kv) {
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) s += j < kv ? v[j] : 0.0f;
+    col[c * kColStride] += s;
+  }
+};
+
 // Reverse sweep.  g = adjoint of the program output per row (zero on padding
-// rows); gacc = this individual's constant accumulators in LDS (binary64).
-template <int K, int D>
+// rows); kv = valid rows of this lane.
+template <int K, int D, class Tape, class Sink>
 __device__ inline void run_reverse(const uint2* __restrict__ prog, int n_uops, int n_tape,
-                                   typename VecT<float, K>::type g, const TapeRef<K>& tape,
-                                   double* gacc, int lane, int kv) {
+                                   typename VecT<float, K>::type g, const Tape& tape, Sink& sink,
+                                   int kv) {
   using V = typename VecT<float, K>::type;
   Slots<V, D> gs;  // adjoints of pushed subtrees
   V gsrc = 0.0f;
@@ -172,123 +243,265 @@ __device__ inline void run_reverse(const uint2* __restrict__ prog, int n_uops, i
     const uint32_t sk = uop_src(h);
     const int ts = tape_src(h), ta = tape_acc(h);
     if (h & HDR_ADJ_SRC) {  // d result / d src
-      if (ts) { gsrc = g * tape.get(--tp); GG_BRANCH(); }
+      if (ts) { --tp; gsrc = g * tape.get(tp); GG_BRANCH(); }
       if (!ts && op == UOP_SUB) { gsrc = -g; GG_BRANCH(); }
       if (!ts && op != UOP_SUB) { gsrc = g; GG_BRANCH(); }  // ADD, RSUB: +1
-      if (sk == SRC_CONST) {
-        const double s = wave_total<K>(gsrc, kv);  // same value on every lane
-        gacc[uop_src_arg(h)] += s;
-        GG_BRANCH();
-      }
+      if (sk == SRC_CONST) { sink.template add<V, K>(uop_src_arg(h), gsrc, kv); GG_BRANCH(); }
       if (sk == SRC_POP) { gs.put(uop_src_arg(h), gsrc); GG_BRANCH(); }
       GG_BRANCH();
     }
     if (h & HDR_ADJ_ACC) {  // d result / d acc operand
-      if (ta) { g = g * tape.get(--tp); GG_BRANCH(); }
+      if (ta) { --tp; g = g * tape.get(tp); GG_BRANCH(); }
       if (!ta && op == UOP_RSUB) { g = -g; GG_BRANCH(); }
       if (!ta && op == UOP_MUL) { g = g * f32_of(u.y); GG_BRANCH(); }  // constant factor
-      if (uop_load(h) == LD_CONST) {
-        const double s = wave_total<K>(g, kv);
-        gacc[uop_load_arg(h)] += s;
-        GG_BRANCH();
-      }
+      if (uop_load(h) == LD_CONST) { sink.template add<V, K>(uop_load_arg(h), g, kv); GG_BRANCH(); }
       GG_BRANCH();
     }
     if (h & HDR_PUSH) { gs.get(uop_push_slot(h), g); GG_BRANCH(); }
   }
 }
 
-template <int K, int D, int W>
-__global__ __launch_bounds__(W * 64) void k_fused_adj(AdjParams p) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int R = p.R;
-  float* xs = reinterpret_cast<float*>(smem_raw);
-  double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
-  double* gacc = yts + R;  // G * C_max
-  const size_t off_ctr = (size_t(p.F) * R * 4 + size_t(R) * 8 + size_t(p.G) * p.C_max * 8 + 15) & ~size_t(15);
-  float* tape_all = reinterpret_cast<float*>(smem_raw + off_ctr + 16);
-
+// Block prologue shared by both kernels: the (span, group) of this block with
+// the same XCD-aware numbering as the forward kernel (consecutive items, which
+// share a span and so the same rows of X, land on one XCD and its L2).
+struct AdjItem {
+  int span, ind0, Gn;
+};
+__device__ inline AdjItem adj_item(const AdjParams& p) {
   const int total = p.n_spans * p.n_groups;
   const int b0 = blockIdx.x;
   const int x = b0 & 7, kk = b0 >> 3, q = total >> 3, r8 = total & 7;
   const int item = x * q + (x < r8 ? x : r8) + kk;
   const int span = item / p.n_groups, grp = item - span * p.n_groups;
   const int ind0 = grp * p.G;
-  const int Gn = min(p.G, p.M - ind0);
+  return {span, ind0, min(p.G, p.M - ind0)};
+}
+
+// Stage one row tile of X (feature-major, zero past the last row) and the
+// centred targets into LDS.
+__device__ inline void adj_stage(const AdjParams& p, float* xs, double* yts, int64_t r0, int nvalid,
+                                 double ybar) {
+  for (int f = 0; f < p.F; ++f) {
+    const float* __restrict__ src = p.X + size_t(f) * p.ldx + r0;
+    for (int r = threadIdx.x; r < p.R; r += blockDim.x) xs[size_t(f) * p.R + r] = r < nvalid ? src[r] : 0.0f;
+  }
+  for (int r = threadIdx.x; r < p.R; r += blockDim.x)
+    yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
+}
+
+// Per-row output adjoint: the residual (s0 - ybar) + s1 p - (y - ybar) in
+// binary64, zero on padding rows.
+template <int K>
+__device__ inline typename VecT<float, K>::type adj_seed(const typename VecT<float, K>::type& v,
+                                                         double s0m, double s1,
+                                                         const double* yts, int lrow, int nvalid) {
+  typename VecT<float, K>::type g;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const bool ok = lrow + j < nvalid;
+    const double res = (s0m + s1 * double(v[j])) - yts[lrow + j];
+    g[j] = ok ? float(res) : 0.0f;
+  }
+  return g;
+}
+
+// Write this block's partials of the individuals `mine` selects.
+template <class Pred>
+__device__ inline void adj_write(const AdjParams& p, const AdjItem& it, const double* gacc, Pred mine) {
+  for (int j = threadIdx.x; j < it.Gn * p.C_max; j += blockDim.x) {
+    const int jj = j / p.C_max, c = j - jj * p.C_max;
+    const int i = it.ind0 + jj;
+    if (mine(i)) p.gpart[(size_t(i) * p.n_spans + it.span) * p.C_max + c] = gacc[j];
+  }
+}
+
+template <int K, int D, int W, int TC>
+__global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int R = p.R;
+  const int CC = p.lane_consts;
+  float* xs = reinterpret_cast<float*>(smem_raw);
+  double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
+  double* gacc = yts + R;                                    // G * C_max
+  float* lacc_all = reinterpret_cast<float*>(gacc + size_t(p.G) * p.C_max);  // W * CC * 65
+
+  const AdjItem it = adj_item(p);
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
   constexpr int BR = 64 * K;
-  TapeRef<K> tape{tape_all + size_t(wv) * p.tape_cap * 64 * K, lane};
+  float* lacc = lacc_all + size_t(wv) * CC * kColStride;
+  LaneSink sink{lacc + lane};
 
-  for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
-  const int64_t span_r0 = int64_t(span) * p.tiles_per_span * R;
-  for (int tile = 0; tile < p.tiles_per_span; ++tile) {
-    const int64_t r0 = span_r0 + int64_t(tile) * R;
-    if (r0 >= p.N) break;
-    const int nvalid = int(min<int64_t>(R, p.N - r0));
+  for (int j = threadIdx.x; j < it.Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
+  const int64_t s_begin = int64_t(it.span) * p.span_rows;
+  const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
+  for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
+    const int nvalid = int(min<int64_t>(R, s_end - r0));
     __syncthreads();
-    for (int f = 0; f < p.F; ++f) {
-      const float* __restrict__ src = p.X + size_t(f) * p.ldx + r0;
-      for (int r = threadIdx.x; r < R; r += blockDim.x) xs[size_t(f) * R + r] = r < nvalid ? src[r] : 0.0f;
-    }
-    for (int r = threadIdx.x; r < R; r += blockDim.x)
-      yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
+    adj_stage(p, xs, yts, r0, nvalid, ybar);
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
-    for (int jj = wv; jj < Gn; jj += W) {  // wave-uniform, see the forward kernel
-      const int i = ind0 + jj;
+    for (int jj = wv; jj < it.Gn; jj += W) {  // wave-uniform trip count
+      const int i = it.ind0 + jj;
       const ProgMeta pm = p.meta[i];
       const double s1 = p.ab[size_t(i) * 2 + 1];
-      const int skip = pm.status != 0 || s1 == 0.0 || pm.n_const == 0 || pm.n_tape > p.tape_cap;
+      const int skip = !adj_active(pm, s1) || !adj_fits_reg(pm, TC, CC);
       if (__builtin_amdgcn_readfirstlane(skip)) continue;
-      const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;  // residual = (s0 - ybar) + s1 p - yt
+      const int nc = __builtin_amdgcn_readfirstlane(pm.n_const);
+      const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
       const uint2* prog = p.uops + size_t(i) * p.U_stride;
-      double* ga = gacc + size_t(jj) * p.C_max;
+      for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
       for (int b = 0; b < nbatch; ++b) {
         const int lrow = b * BR + lane * K;
-        typename VecT<float, K>::type g;
+        RegTape<K, TC> tape;
         const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const bool ok = lrow + j < nvalid;
-          const double res = (s0m + s1 * double(v[j])) - yts[lrow + j];
-          g[j] = ok ? float(res) : 0.0f;
-        }
+        const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
         const int kv = max(0, min(K, nvalid - lrow));
-        run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, ga, lane, kv);
+        run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
+      }
+      // the wave's column writes must land before lane c reads column c
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < nc) {
+        const float* colc = lacc + lane * kColStride;
+        double s0 = 0.0, s1r = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < 64; k += 4) {
+          s0 += double(colc[k]);
+          s1r += double(colc[k + 1]);
+          s2 += double(colc[k + 2]);
+          s3 += double(colc[k + 3]);
+        }
+        gacc[size_t(jj) * p.C_max + lane] += (s0 + s1r) + (s2 + s3);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __syncthreads();
+  adj_write(p, it, gacc, [&](int i) {
+    const ProgMeta pm = p.meta[i];
+    return adj_active(pm, p.ab[size_t(i) * 2 + 1]) && adj_fits_reg(pm, TC, CC);
+  });
+}
+
+template <int K, int D, int W>
+__global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int R = p.R;
+  const int TC = p.reg_tape, CC = p.lane_consts;
+  // skip the whole block unless one of its individuals belongs to this kernel
+  __shared__ int any;
+  const AdjItem it = adj_item(p);
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int jj = 0; jj < it.Gn; ++jj) {
+      const ProgMeta pm = p.meta[it.ind0 + jj];
+      n += adj_active(pm, p.ab[size_t(it.ind0 + jj) * 2 + 1]) && !adj_fits_reg(pm, TC, CC);
+    }
+    any = n;
+  }
+  __syncthreads();
+  if (any == 0) return;
+
+  float* xs = reinterpret_cast<float*>(smem_raw);
+  double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
+  double* gacc = yts + R;  // G * C_max
+  const size_t off_tape = (size_t(p.F) * R * 4 + size_t(R) * 8 + size_t(p.G) * p.C_max * 8 + 15) & ~size_t(15);
+  float* tape_all = reinterpret_cast<float*>(smem_raw + off_tape);
+
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const double ybar = p.stats[ST_YBAR];
+  constexpr int BR = 64 * K;
+  LdsTape<K> tape{tape_all + size_t(wv) * p.tape_cap * 64 * K, lane};
+
+  for (int j = threadIdx.x; j < it.Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
+  const int64_t s_begin = int64_t(it.span) * p.span_rows;
+  const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
+  for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
+    const int nvalid = int(min<int64_t>(R, s_end - r0));
+    __syncthreads();
+    adj_stage(p, xs, yts, r0, nvalid, ybar);
+    __syncthreads();
+    const int nbatch = (nvalid + BR - 1) / BR;
+    for (int jj = wv; jj < it.Gn; jj += W) {  // wave-uniform trip count
+      const int i = it.ind0 + jj;
+      const ProgMeta pm = p.meta[i];
+      const double s1 = p.ab[size_t(i) * 2 + 1];
+      const int skip = !adj_active(pm, s1) || adj_fits_reg(pm, TC, CC) || pm.n_tape > p.tape_cap;
+      if (__builtin_amdgcn_readfirstlane(skip)) continue;
+      const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
+      const uint2* prog = p.uops + size_t(i) * p.U_stride;
+      WaveSink sink{gacc + size_t(jj) * p.C_max};
+      for (int b = 0; b < nbatch; ++b) {
+        const int lrow = b * BR + lane * K;
+        const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
+        const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
+        const int kv = max(0, min(K, nvalid - lrow));
+        run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
       }
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) {
-    const int jj = j / p.C_max, c = j - jj * p.C_max;
-    p.gpart[(size_t(ind0 + jj) * p.n_spans + span) * p.C_max + c] = gacc[j];
-  }
+  adj_write(p, it, gacc, [&](int i) {
+    const ProgMeta pm = p.meta[i];
+    return adj_active(pm, p.ab[size_t(i) * 2 + 1]) && !adj_fits_reg(pm, TC, CC);
+  });
 }
 
-template <int K, int D, int W>
-static hipError_t adj_impl(const TileCfg& c, const AdjParams& ap, hipStream_t s) {
-  const size_t sh = adjoint_lds_bytes(ap.F, ap.R, ap.G, ap.C_max, W, K, ap.tape_cap);
-  const int nb = c.n_spans * c.n_groups;
-  hipLaunchKernelGGL((k_fused_adj<K, D, W>), dim3(nb), dim3(W * 64), sh, s, ap);
+template <int K, int D, int W, int TC>
+static hipError_t reg_impl(const AdjPlan& a, const AdjParams& ap, hipStream_t s) {
+  const size_t sh = adjoint_reg_lds_bytes(ap.F, a.reg.R, a.reg.G, ap.C_max, W, a.lane_consts);
+  const int nb = a.n_spans * a.reg.n_groups;
+  hipLaunchKernelGGL((k_adj_reg<K, D, W, TC>), dim3(nb), dim3(W * 64), sh, s, ap);
   return hipGetLastError();
 }
 
-hipError_t launch_fused_adjoint(const TileCfg& c, const uint2* uops, int U_stride,
-                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                                const double* stats, const double* ab, double* gpart,
-                                float* tape_spill, int tape_lds, hipStream_t s) {
-  (void)tape_spill;
-  AdjParams ap{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
-               c.R, c.G, c.n_groups, c.n_spans, c.tiles_per_span, tape_lds};
-  if (c.D != 8) return hipErrorInvalidValue;
-  if (c.K == 2 && c.W == 4) return adj_impl<2, 8, 4>(c, ap, s);
-  if (c.K == 2 && c.W == 2) return adj_impl<2, 8, 2>(c, ap, s);
-  if (c.K == 2 && c.W == 1) return adj_impl<2, 8, 1>(c, ap, s);
-  if (c.K == 1 && c.W == 4) return adj_impl<1, 8, 4>(c, ap, s);
-  if (c.K == 1 && c.W == 2) return adj_impl<1, 8, 2>(c, ap, s);
-  if (c.K == 1 && c.W == 1) return adj_impl<1, 8, 1>(c, ap, s);
+template <int K, int D, int W>
+static hipError_t lds_impl(const AdjPlan& a, const AdjParams& ap, hipStream_t s) {
+  const size_t sh = adjoint_lds_bytes(ap.F, a.wide.R, a.wide.G, ap.C_max, W, K, ap.tape_cap);
+  const int nb = a.n_spans * a.wide.n_groups;
+  hipLaunchKernelGGL((k_adj_lds<K, D, W>), dim3(nb), dim3(W * 64), sh, s, ap);
+  return hipGetLastError();
+}
+
+static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, const uint2* uops, int U_stride,
+                            const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                            const double* stats, const double* ab, double* gpart) {
+  return AdjParams{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
+                   c.R, c.G, c.n_groups, a.n_spans, a.span_rows, a.tape_cap, a.reg_tape,
+                   a.lane_consts};
+}
+
+hipError_t launch_adjoint_reg(const AdjPlan& a, const uint2* uops, int U_stride,
+                              const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                              const double* stats, const double* ab, double* gpart, hipStream_t s) {
+  const AdjParams ap = adj_params(a, a.reg, uops, U_stride, meta, M, C_max, d, stats, ab, gpart);
+  const TileCfg& r = a.reg;
+  if (r.W != 4) return hipErrorInvalidValue;
+  if (r.K == 4 && a.reg_tape == 16 && r.D == 4) return reg_impl<4, 4, 4, 16>(a, ap, s);
+  if (r.K == 4 && a.reg_tape == 16 && r.D == 8) return reg_impl<4, 8, 4, 16>(a, ap, s);
+  if (r.K == 2 && a.reg_tape == 32 && r.D == 4) return reg_impl<2, 4, 4, 32>(a, ap, s);
+  if (r.K == 2 && a.reg_tape == 32 && r.D == 8) return reg_impl<2, 8, 4, 32>(a, ap, s);
+  return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
+}
+
+hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
+                              const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                              const double* stats, const double* ab, double* gpart, hipStream_t s) {
+  const AdjParams ap = adj_params(a, a.wide, uops, U_stride, meta, M, C_max, d, stats, ab, gpart);
+  const TileCfg& w = a.wide;
+  if (w.D != 8) return hipErrorInvalidValue;
+  if (w.K == 2 && w.W == 4) return lds_impl<2, 8, 4>(a, ap, s);
+  if (w.K == 2 && w.W == 2) return lds_impl<2, 8, 2>(a, ap, s);
+  if (w.K == 2 && w.W == 1) return lds_impl<2, 8, 1>(a, ap, s);
+  if (w.K == 1 && w.W == 4) return lds_impl<1, 8, 4>(a, ap, s);
+  if (w.K == 1 && w.W == 2) return lds_impl<1, 8, 2>(a, ap, s);
+  if (w.K == 1 && w.W == 1) return lds_impl<1, 8, 1>(a, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 

@@ -67,11 +67,25 @@ hipError_t launch_plain_forward(bool fp64, const TileCfg& c, int i, const uint2*
                                 double* ab, hipStream_t s);
 int plain_blocks(const TileCfg& c, int64_t N);
 
-// adjoint: gradient partials gpart[i][span][C_max]
-hipError_t launch_fused_adjoint(const TileCfg& c, const uint2* uops, int U_stride,
-                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                                const double* stats, const double* ab, double* gpart,
-                                float* tape_spill, int tape_lds, hipStream_t s);
+// Adjoint launch plan: the register-tape kernel (reg) and the LDS-tape kernel
+// (wide) cut the rows into the same n_spans spans of span_rows rows.
+struct AdjPlan {
+  TileCfg reg, wide;
+  int n_spans = 1;
+  int64_t span_rows = 0;
+  int reg_tape = 16;     // register tape entries of the reg kernel
+  int lane_consts = 16;  // per-lane constant columns of the reg kernel
+  int tape_cap = 1;      // LDS tape entries per wave of the wide kernel
+};
+
+// adjoint: gradient partials gpart[i][span][C_max]; both kernels must run
+// (each writes the partials of the individuals it owns)
+hipError_t launch_adjoint_reg(const AdjPlan& a, const uint2* uops, int U_stride,
+                              const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                              const double* stats, const double* ab, double* gpart, hipStream_t s);
+hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
+                              const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                              const double* stats, const double* ab, double* gpart, hipStream_t s);
 hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const double* gpart,
                                 int n_spans, const double* stats, const double* ab,
                                 uint32_t flags, const int8_t* status, double* grad,
@@ -81,11 +95,16 @@ int lds_limit_bytes();
 int measure_op_costs(double* out, int n, int iters, hipStream_t s, float* scratch);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 
-// LDS bytes of one adjoint block (row tile, centred targets, constant
-// accumulators, counter, W wave tapes of tape_cap entries x 64 lanes x K rows).
+// LDS bytes of one LDS-tape adjoint block (row tile, centred targets,
+// constant accumulators, W wave tapes of tape_cap entries x 64 lanes x K rows).
 inline size_t adjoint_lds_bytes(int F, int R, int G, int C_max, int W, int K, int tape_cap) {
   const size_t off = (size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * C_max * 8 + 15) & ~size_t(15);
-  return off + 16 + size_t(W) * tape_cap * 64 * K * 4;
+  return off + size_t(W) * tape_cap * 64 * K * 4;
+}
+// LDS bytes of one register-tape adjoint block (row tile, centred targets,
+// constant accumulators, W waves x CC per-lane constant columns of 65 floats).
+inline size_t adjoint_reg_lds_bytes(int F, int R, int G, int C_max, int W, int CC) {
+  return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * C_max * 8 + size_t(W) * CC * 65 * 4;
 }
 inline size_t forward_lds_bytes(int F, int R, int G) {
   return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * 4 * 8 + 16;

@@ -84,11 +84,11 @@ def test_aux_outputs_match_oracle():
     assert okr.sum() > 40
     np.testing.assert_allclose(aux[okr, 2], ref["mse"][okr], rtol=1e-5)
     np.testing.assert_allclose(aux[ok, 3], ref["nmse"][ok], rtol=1e-5, atol=1e-10)
-    # the slope b is well-conditioned only when p explains part of y:
-    # rho^2 = 1 - LS-MSE/Var(y) >= 0.01
+    # the slope b = S_py / S_pp loses about -log10|rho| digits, where
+    # rho^2 = 1 - LS-MSE/Var(y): held to 1e-4 where rho^2 >= 1e-4
     vy = float(np.var(d["y"].astype(np.float64)))
-    corr = ok & (ref["b"] != 0) & (ref["fitness"] <= 0.99 * vy)
-    assert corr.sum() > 10
+    corr = ok & (ref["b"] != 0) & (ref["fitness"] <= (1.0 - 1e-4) * vy)
+    assert corr.sum() >= 20
     np.testing.assert_allclose(aux[corr, 1], ref["b"][corr], rtol=1e-4)
 
 

@@ -41,6 +41,26 @@ def test_ls_scale_and_offset_constants_have_zero_gradient():
     assert abs(gr[2]) > 1e-3
 
 
+def test_gradient_term_magnitudes():
+    """gabs of p = c * x0 with raw MSE is (2/N) sum |(c x - y) x|, written out;
+    and |g| <= gabs always (triangle inequality)."""
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (1, 300))
+    y = 0.5 * X[0] + rng.normal(0, 0.1, 300)
+    c = 1.25
+    g, gc = genotype([C, V0, O.MUL], [c])
+    s, gr = GR.gradient(g, gc, 5, X, y, linear_scaling=False, rng="f64")
+    want = 2.0 / 300 * sum(abs((c * X[0, r] - y[r]) * X[0, r]) for r in range(300))
+    assert s["gabs"][0] == pytest.approx(want, rel=1e-13)
+    assert abs(gr[0]) <= s["gabs"][0]
+    toks = [C, C, C, V0, O.MUL, V1, O.ADD, O.SIN, O.MUL, O.ADD]
+    X2 = rng.uniform(-1, 1, (2, 400))
+    g2, gc2 = genotype(toks, [0.3, 1.7, 1.4])
+    s2, gr2 = GR.gradient(g2, gc2, 5, X2, X2[0] ** 2, rng="f64")
+    assert np.all(np.abs(gr2) <= s2["gabs"] * (1 + 1e-12))
+    assert s2["gabs"][0] > 1e3 * abs(gr2[0])   # the absorbed offset cancels
+
+
 @pytest.mark.parametrize("op", range(11))
 def test_each_operator_partial(op):
     """d op / d a (and d b) against central differences of opset.apply."""
