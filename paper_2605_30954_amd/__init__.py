@@ -18,7 +18,7 @@ from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  #
                    MAX_LEN, MAX_CONSTS, MAX_FEATURES, check, last_error, lib)
 
 __all__ = ["eval_batch", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
-           "autotune", "clear_graphs", "flags_of", "profile", "profile_report", "op_costs",
+           "autotune", "load_tuning", "clear_graphs", "flags_of", "profile", "profile_report", "op_costs",
            "GPGOMEAFitness", "LibraryError"]
 
 
@@ -151,11 +151,15 @@ def grad_consts(ops, consts, X, y, linear_scaling=True, plain=False, graph=True,
     return tuple(out)
 
 
-def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path=None, trials=3):
-    """Time the fused kernels' launch parameters on these inputs and keep the
-    fastest for this problem class; returns the library's description."""
+def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path=None, trials=3,
+             fp64_nodes=False):
+    """Time the fused kernels' launch parameters (rows per lane, rows per LDS
+    tile, individuals per block) on these inputs and keep the fastest for this
+    problem class in the process; with ``cache_path`` also merge the choice
+    into that file.  Synchronises the current stream.  Returns the library's
+    one-line description of the choice."""
     ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
-    flags = flags_of(linear_scaling)
+    flags = flags_of(linear_scaling, fp64_nodes)
     ws = _workspace(dev, workspace_bytes(M, L, C, F, N, flags))
     desc = ctypes.create_string_buffer(512)
     check(lib.gpgomea_autotune(
@@ -163,6 +167,14 @@ def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path
         y.data_ptr(), flags, int(bool(with_grad)), ws.data_ptr(), ws.numel(),
         cache_path.encode() if cache_path else None, int(trials), desc, 512, _stream_ptr(dev)))
     return desc.value.decode()
+
+
+def load_tuning(cache_path):
+    """Load a tuning file written by autotune; returns the number of entries."""
+    n = lib.gpgomea_load_tuning(str(cache_path).encode())
+    if n < 0:
+        raise LibraryError(n, last_error())
+    return n
 
 
 def clear_graphs():

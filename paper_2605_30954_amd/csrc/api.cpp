@@ -69,7 +69,7 @@ int adj_span_cap(const Shape& s) {
 }
 
 struct Layout {
-  size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, total;
+  size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, tune, total;
   int U_stride;
 };
 
@@ -95,6 +95,8 @@ Layout layout_of(const Shape& s) {
   o = align256(o + 64);
   l.gpart = o;
   o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
+  l.tune = o;  // outputs of the autotuner's trial calls: fitness, grad, status
+  o = align256(o + size_t(s.M) * (std::max(s.C_max, 1) + 2) * sizeof(double));
   l.total = o;
   return l;
 }
@@ -144,6 +146,8 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
     c.K = fp64 ? 4 : t->K;
     c.R = t->R;
     c.G = t->G;
+    const int64_t Nt = (s.N + 64 * c.K - 1) / (64 * c.K) * (64 * c.K);
+    if (Nt < c.R) c.R = int(Nt);
   } else {
     c.R = 2048;
     while (c.R > BR && forward_lds_bytes(s.F, c.R, 64) > size_t(forward_lds_cap())) c.R /= 2;
@@ -181,13 +185,18 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   }
   a.lane_consts = std::min(Cm, 32);
   r.G = 16;
-  const int BRr = 64 * r.K;
   r.R = 1024;
   if (t) {
+    if (t->K == 2 || t->K == 4) {
+      r.K = t->K;
+      a.reg_tape = t->K == 4 ? 16 : 32;
+    }
     r.R = t->R;
     r.G = t->G;
   }
-  while (r.R > BRr && (size_t(s.F) * r.R * 4 + size_t(r.R) * 8 > 32 * 1024 ||
+  const int BRr = 64 * r.K;
+  const size_t tile_cap = t ? size_t(cap) : size_t(32 * 1024);  // untuned: room for 3+ blocks/CU
+  while (r.R > BRr && (size_t(s.F) * r.R * 4 + size_t(r.R) * 8 > tile_cap ||
                        adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts) > size_t(cap)))
     r.R /= 2;
   const int64_t Nr = (s.N + BRr - 1) / BRr * BRr;
@@ -204,9 +213,12 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   a.n_spans = int((s.N + a.span_rows - 1) / a.span_rows);
   r.n_spans = a.n_spans;
 
-  // LDS-tape kernel: its tile must divide span_rows (powers of two <= r.R)
+  // LDS-tape kernel: its tile must divide span_rows (powers of two <= r.R).
+  // A program of L tokens has at most L - 1 tape entries (one per tree edge)
+  // and at most C_max constants, so small shapes never need it.
   TileCfg& w = a.wide;
   a.tape_cap = std::max(1, s.L_max - 1);
+  a.need_wide = a.tape_cap > a.reg_tape || Cm > a.lane_consts;
   w.D = 8;
   bool ok = false;
   const int Ks[2] = {2, 1};
@@ -245,6 +257,7 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
 }
 
 bool adjoint_plan_fits(const Shape& s, const AdjPlan& a) {
+  if (!a.need_wide) return true;
   const int cap = lds_limit_bytes() - 64;
   return adjoint_lds_bytes(s.F, a.wide.R, a.wide.G, std::max(1, s.C_max), a.wide.W, a.wide.K,
                            a.tape_cap) <= size_t(cap) &&
@@ -347,8 +360,9 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
         double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
         GG_TIMED("plain_adjoint", launch_adjoint_reg(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
                                                      ab + 2 * size_t(i), gi, c.stream));
-        GG_TIMED("plain_adjoint_lds", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
-                                                         ab + 2 * size_t(i), gi, c.stream));
+        if (one.need_wide)
+          GG_TIMED("plain_adjoint_lds", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
+                                                           stats, ab + 2 * size_t(i), gi, c.stream));
       }
       GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
                                                      c.s.flags, c.status, c.grad, c.stream));
@@ -362,8 +376,9 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   if (c.with_grad) {
     GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
                                                gpart, c.stream));
-    GG_TIMED("adjoint_lds", launch_adjoint_lds(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                               gpart, c.stream));
+    if (ac.need_wide)
+      GG_TIMED("adjoint_lds", launch_adjoint_lds(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
+                                                 gpart, c.stream));
     GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab,
                                                    c.s.flags, c.status, c.grad, c.stream));
   }
@@ -545,18 +560,217 @@ extern "C" int gpgomea_op_costs(double* out, int32_t n, int32_t iters, float* de
 }
 
 // ------------------------------------------------------------------ tuning
+// ------------------------------------------------------------------ autotune
+namespace {
+
+constexpr int64_t kTuneRows = int64_t(1) << 20;  // rows the trial calls use at most
+
+// Fastest of `trials` timed runs of the whole pipeline under the given plans
+// (after one untimed run), in ms; negative on a HIP error.
+float time_plans(const Call& c, const TileCfg& fc, const AdjPlan& ac, int trials) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0f;
+  float best = -1.0f;
+  if (enqueue_fused(c, fc, ac) == GPGOMEA_OK) {
+    best = 1e30f;
+    for (int t = 0; t < trials; ++t) {
+      float ms = 0.0f;
+      if (hipEventRecord(e0, c.stream) != hipSuccess || enqueue_fused(c, fc, ac) != GPGOMEA_OK ||
+          hipEventRecord(e1, c.stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        best = -1.0f;
+        break;
+      }
+      best = std::min(best, ms);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+std::string tune_line(const char* table, const TuneKey& k, const Tuned& t) {
+  char b[256];
+  std::snprintf(b, sizeof(b),
+                "  {\"table\": \"%s\", \"fp64\": %d, \"Lcls\": %d, \"F\": %d, \"Ncls\": %d, "
+                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d}",
+                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G);
+  return b;
+}
+
+bool json_int(const std::string& line, const char* key, int* out) {
+  const std::string pat = std::string("\"") + key + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return false;
+  char* end = nullptr;
+  const long v = std::strtol(line.c_str() + at + pat.size(), &end, 10);
+  if (end == line.c_str() + at + pat.size()) return false;
+  *out = int(v);
+  return true;
+}
+
+// Read a tuning file (one entry per line) into the tables; false if unreadable.
+bool read_tuning(const char* path, int* n_read) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  int n = 0;
+  while (std::getline(f, line)) {
+    const bool fwd = line.find("\"table\": \"fwd\"") != std::string::npos;
+    const bool adj = line.find("\"table\": \"adj\"") != std::string::npos;
+    if (!fwd && !adj) continue;
+    TuneKey k{};
+    Tuned t{};
+    if (!(json_int(line, "fp64", &k.fp64) && json_int(line, "Lcls", &k.Lcls) &&
+          json_int(line, "F", &k.F) && json_int(line, "Ncls", &k.Ncls) &&
+          json_int(line, "Mcls", &k.Mcls) && json_int(line, "grad", &k.grad) &&
+          json_int(line, "K", &t.K) && json_int(line, "R", &t.R) && json_int(line, "G", &t.G)))
+      continue;
+    if (t.K < 1 || t.R < 64 || t.G < 1) continue;
+    (fwd ? g_tuned : g_tuned_adj)[k] = t;
+    ++n;
+  }
+  if (n_read) *n_read = n;
+  return true;
+}
+
+bool write_tuning(const char* path) {
+  std::ostringstream o;
+  o << "{\"gpgomea_tuning\": 1, \"entries\": [\n";
+  bool first = true;
+  for (const auto& e : g_tuned) {
+    o << (first ? "" : ",\n") << tune_line("fwd", e.first, e.second);
+    first = false;
+  }
+  for (const auto& e : g_tuned_adj) {
+    o << (first ? "" : ",\n") << tune_line("adj", e.first, e.second);
+    first = false;
+  }
+  o << "\n]}\n";
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return false;
+  f << o.str();
+  return bool(f);
+}
+
+}  // namespace
+
 extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
                                 int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
                                 const float* y, uint32_t flags, int32_t with_grad, void* workspace,
                                 size_t workspace_bytes, const char* cache_path, int32_t trials,
                                 char* out_desc, int32_t desc_len, void* stream) {
-  (void)ops; (void)M; (void)L_max; (void)consts; (void)C_max; (void)X; (void)F; (void)N;
-  (void)ldx; (void)y; (void)flags; (void)with_grad; (void)workspace; (void)workspace_bytes;
-  (void)cache_path; (void)trials; (void)out_desc; (void)desc_len; (void)stream;
-  return fail(GPGOMEA_E_UNSUPPORTED, "autotune not built yet");
+  const Shape s{M, L_max, C_max, F, N, ldx, flags};
+  if (flags & GPGOMEA_PLAIN) return fail(GPGOMEA_E_ARG, "autotune tunes the fused form (PLAIN set)");
+  if (with_grad && (flags & GPGOMEA_FP64_NODES))
+    return fail(GPGOMEA_E_UNSUPPORTED, "the adjoint runs in binary32 nodes only");
+  if (trials < 1) return fail(GPGOMEA_E_ARG, "trials=%d must be >= 1", trials);
+  const Layout l = layout_of(s);
+  char* ws = static_cast<char*>(workspace);
+  double* fit = reinterpret_cast<double*>(ws + l.tune);
+  int rc = check_call(s, ops, consts, X, y, fit, workspace, workspace_bytes);
+  if (rc) return rc;
+  (void)hipGetLastError();
+  // trial calls run on a prefix of the rows; the choice is stored for the
+  // full shape's class
+  Shape st = s;
+  st.N = std::min<int64_t>(s.N, kTuneRows);
+  st.flags = (flags & ~GPGOMEA_NO_GRAPH) | GPGOMEA_NO_GRAPH;
+  const bool fp64 = (flags & GPGOMEA_FP64_NODES) != 0;
+  double* grad = fit + M;
+  int8_t* status = reinterpret_cast<int8_t*>(grad + size_t(M) * std::max(C_max, 1));
+  Call c{st, ops, consts, X, y, fit, nullptr, nullptr, status, ws, static_cast<hipStream_t>(stream),
+         false};
+
+  // forward: rows per lane K, rows per LDS tile R, individuals per block G
+  const int Ks_f[2] = {8, 4};
+  const int Rs_f[5] = {256, 512, 1024, 2048, 4096};
+  const int Gs_f[5] = {4, 8, 16, 32, 64};
+  const int lds = lds_limit_bytes();
+  Tuned best_f{0, 0, 0};
+  float best_f_ms = 1e30f;
+  TileCfg fc_best;
+  for (int k : Ks_f) {
+    if (fp64 && k != 4) continue;
+    for (int r : Rs_f) {
+      if (r < 64 * k) continue;
+      for (int g : Gs_f) {
+        if (forward_lds_bytes(F, r, g) > size_t(lds)) continue;
+        const Tuned t{k, r, g};
+        const TileCfg fc = plan_forward(st, &t);
+        const AdjPlan ac = plan_adjoint(st, fc.D, nullptr, adj_span_cap(s));
+        const float ms = time_plans(c, fc, ac, trials);
+        if (ms < 0.0f) {
+          const std::string why = last_error();
+          return fail(GPGOMEA_E_HIP, "autotune trial failed: %s", why.c_str());
+        }
+        if (ms < best_f_ms) {
+          best_f_ms = ms;
+          best_f = t;
+          fc_best = fc;
+        }
+      }
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[tune_key(s, false)] = best_f;
+  char desc[512];
+  int len = std::snprintf(desc, sizeof(desc), "forward K=%d R=%d G=%d (%.3f ms on %lld rows)", best_f.K,
+                          best_f.R, best_f.G, double(best_f_ms), (long long)st.N);
+
+  if (with_grad) {
+    c.with_grad = true;
+    c.grad = grad;
+    const int Ks_a[2] = {4, 2};
+    const int Rs_a[4] = {256, 512, 1024, 2048};
+    const int Gs_a[4] = {4, 8, 16, 32};
+    Tuned best_a{0, 0, 0};
+    float best_a_ms = 1e30f;
+    for (int k : Ks_a) {
+      for (int r : Rs_a) {
+        if (r < 64 * k) continue;
+        for (int g : Gs_a) {
+          const Tuned t{k, r, g};
+          const AdjPlan ac = plan_adjoint(st, fc_best.D, &t, adj_span_cap(s));
+          if (ac.reg.R != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
+          const float ms = time_plans(c, fc_best, ac, trials);
+          if (ms < 0.0f) {
+            const std::string why = last_error();
+            return fail(GPGOMEA_E_HIP, "autotune trial failed: %s", why.c_str());
+          }
+          if (ms < best_a_ms) {
+            best_a_ms = ms;
+            best_a = t;
+          }
+        }
+      }
+    }
+    if (best_a.K) {
+      g_tuned_adj[tune_key(s, true)] = best_a;
+      len += std::snprintf(desc + len, sizeof(desc) - size_t(len),
+                           "; fitness+gradient with adjoint K=%d R=%d G=%d (%.3f ms)", best_a.K,
+                           best_a.R, best_a.G, double(best_a_ms));
+    }
+  }
+  if (cache_path) {
+    int n = 0;
+    std::map<TuneKey, Tuned> keep_f = g_tuned, keep_a = g_tuned_adj;
+    (void)read_tuning(cache_path, &n);  // merge: entries of this process win
+    for (const auto& e : keep_f) g_tuned[e.first] = e.second;
+    for (const auto& e : keep_a) g_tuned_adj[e.first] = e.second;
+    if (!write_tuning(cache_path)) return fail(GPGOMEA_E_ARG, "cannot write %s", cache_path);
+  }
+  if (out_desc && desc_len > 0) {
+    std::strncpy(out_desc, desc, size_t(desc_len) - 1);
+    out_desc[desc_len - 1] = '\0';
+  }
+  return GPGOMEA_OK;
 }
 
 extern "C" int gpgomea_load_tuning(const char* cache_path) {
-  (void)cache_path;
-  return fail(GPGOMEA_E_UNSUPPORTED, "autotune not built yet");
+  if (!cache_path) return fail(GPGOMEA_E_ARG, "cache_path is NULL");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int n = 0;
+  if (!read_tuning(cache_path, &n)) return fail(GPGOMEA_E_ARG, "cannot read %s", cache_path);
+  return n;
 }

@@ -388,29 +388,33 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   });
 }
 
+// LDS-tape kernel: only the individuals the register kernel cannot take.
+// They are rare, so all W waves share each one: wave w takes batches w, w+W,
+// ... of a tile and adds its constant adjoints to its own copy of the
+// accumulators; the copies are summed in wave order at the end (bitwise
+// repeatable).  A block whose group holds none of them exits at once.
 template <int K, int D, int W>
 __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R = p.R;
   const int TC = p.reg_tape, CC = p.lane_consts;
-  // skip the whole block unless one of its individuals belongs to this kernel
   __shared__ int any;
   const AdjItem it = adj_item(p);
-  if (threadIdx.x == 0) {
-    int n = 0;
-    for (int jj = 0; jj < it.Gn; ++jj) {
-      const ProgMeta pm = p.meta[it.ind0 + jj];
-      n += adj_active(pm, p.ab[size_t(it.ind0 + jj) * 2 + 1]) && !adj_fits_reg(pm, TC, CC);
-    }
-    any = n;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (int(threadIdx.x) < it.Gn) {
+    const int i = it.ind0 + threadIdx.x;
+    const ProgMeta pm = p.meta[i];
+    if (adj_active(pm, p.ab[size_t(i) * 2 + 1]) && !adj_fits_reg(pm, TC, CC)) any = 1;
   }
   __syncthreads();
   if (any == 0) return;
 
   float* xs = reinterpret_cast<float*>(smem_raw);
   double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
-  double* gacc = yts + R;  // G * C_max
-  const size_t off_tape = (size_t(p.F) * R * 4 + size_t(R) * 8 + size_t(p.G) * p.C_max * 8 + 15) & ~size_t(15);
+  double* gacc = yts + R;  // W copies of G * C_max
+  const size_t off_tape =
+      (size_t(p.F) * R * 4 + size_t(R) * 8 + size_t(W) * p.G * p.C_max * 8 + 15) & ~size_t(15);
   float* tape_all = reinterpret_cast<float*>(smem_raw + off_tape);
 
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -418,8 +422,9 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
   const double ybar = p.stats[ST_YBAR];
   constexpr int BR = 64 * K;
   LdsTape<K> tape{tape_all + size_t(wv) * p.tape_cap * 64 * K, lane};
+  const int GC = p.G * p.C_max;
 
-  for (int j = threadIdx.x; j < it.Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
+  for (int j = threadIdx.x; j < W * GC; j += blockDim.x) gacc[j] = 0.0;
   const int64_t s_begin = int64_t(it.span) * p.span_rows;
   const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
   for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
@@ -428,7 +433,7 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
     adj_stage(p, xs, yts, r0, nvalid, ybar);
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
-    for (int jj = wv; jj < it.Gn; jj += W) {  // wave-uniform trip count
+    for (int jj = 0; jj < it.Gn; ++jj) {  // uniform over the block
       const int i = it.ind0 + jj;
       const ProgMeta pm = p.meta[i];
       const double s1 = p.ab[size_t(i) * 2 + 1];
@@ -436,8 +441,8 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
       if (__builtin_amdgcn_readfirstlane(skip)) continue;
       const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
       const uint2* prog = p.uops + size_t(i) * p.U_stride;
-      WaveSink sink{gacc + size_t(jj) * p.C_max};
-      for (int b = 0; b < nbatch; ++b) {
+      WaveSink sink{gacc + size_t(wv) * GC + size_t(jj) * p.C_max};
+      for (int b = wv; b < nbatch; b += W) {
         const int lrow = b * BR + lane * K;
         const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
         const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
@@ -447,6 +452,10 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
     }
   }
   __syncthreads();
+  for (int j = threadIdx.x; j < GC; j += blockDim.x) {
+#pragma unroll
+    for (int w = 1; w < W; ++w) gacc[j] += gacc[size_t(w) * GC + j];
+  }
   adj_write(p, it, gacc, [&](int i) {
     const ProgMeta pm = p.meta[i];
     return adj_active(pm, p.ab[size_t(i) * 2 + 1]) && !adj_fits_reg(pm, TC, CC);

@@ -76,6 +76,7 @@ struct AdjPlan {
   int reg_tape = 16;     // register tape entries of the reg kernel
   int lane_consts = 16;  // per-lane constant columns of the reg kernel
   int tape_cap = 1;      // LDS tape entries per wave of the wide kernel
+  bool need_wide = true; // some program of this shape may exceed the reg kernel
 };
 
 // adjoint: gradient partials gpart[i][span][C_max]; both kernels must run
@@ -95,10 +96,12 @@ int lds_limit_bytes();
 int measure_op_costs(double* out, int n, int iters, hipStream_t s, float* scratch);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 
-// LDS bytes of one LDS-tape adjoint block (row tile, centred targets,
-// constant accumulators, W wave tapes of tape_cap entries x 64 lanes x K rows).
+// LDS bytes of one LDS-tape adjoint block (row tile, centred targets, W
+// copies of the constant accumulators, W wave tapes of tape_cap entries x 64
+// lanes x K rows).
 inline size_t adjoint_lds_bytes(int F, int R, int G, int C_max, int W, int K, int tape_cap) {
-  const size_t off = (size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * C_max * 8 + 15) & ~size_t(15);
+  const size_t off =
+      (size_t(F) * R * 4 + size_t(R) * 8 + size_t(W) * G * C_max * 8 + 15) & ~size_t(15);
   return off + size_t(W) * tape_cap * 64 * K * 4;
 }
 // LDS bytes of one register-tape adjoint block (row tile, centred targets,

@@ -154,3 +154,21 @@ def test_single_hip_runtime_in_process():
     import torch  # noqa: F401
     rts = _lib.hip_runtimes()
     assert len(rts) == 1, rts
+
+
+def test_tuning_file_roundtrip(tmp_path):
+    """A tuning file is read line by line; malformed entries are skipped and an
+    unreadable path is an argument error."""
+    import paper_2605_30954_amd as gg
+    f = tmp_path / "tune.json"
+    f.write_text('{"gpgomea_tuning": 1, "entries": [\n'
+                 '  {"table": "fwd", "fp64": 0, "Lcls": 5, "F": 10, "Ncls": 16, "Mcls": 10, "grad": 0, '
+                 '"K": 8, "R": 1024, "G": 16},\n'
+                 '  {"table": "adj", "fp64": 0, "Lcls": 5, "F": 10, "Ncls": 16, "Mcls": 10, "grad": 1, '
+                 '"K": 4, "R": 512, "G": 16},\n'
+                 '  {"table": "adj", "fp64": 0, "Lcls": 5, "F": 10},\n'
+                 '  {"table": "fwd", "fp64": 0, "Lcls": 5, "F": 10, "Ncls": 16, "Mcls": 10, "grad": 0, '
+                 '"K": 0, "R": 1024, "G": 16}\n]}\n')
+    assert gg.load_tuning(f) == 2
+    with pytest.raises(gg.LibraryError):
+        gg.load_tuning(tmp_path / "missing.json")
