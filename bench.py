@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (planner defaults)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device-to-device 3 times "
+                         "(a plain copy of known size, to scale HBM traffic counters)")
     ap.add_argument("--tune-cache", default=None,
                     help="tuning file: loaded if it exists, else written by the autotuner")
     return ap.parse_args()
@@ -96,14 +99,16 @@ def roofline(gg, ops, cfg, N, stream, step, steps):
     gg.profile(False)
     per = {k: v[1] / steps for k, v in rep.items()}          # ms per step
     launches = {k: v[0] / steps for k, v in rep.items()}
-    # the two adjoint kernels split the individuals between them: one launch pair
-    adj_ms = per.get("adjoint_reg", 0.0) + per.get("adjoint_lds", 0.0)
+    # the adjoint's tier kernels split the individuals between them (after a
+    # partition kernel that lists each tier): together they are one launch
+    adj_parts = ("adjoint_partition", "adjoint_reg", "adjoint_reg_b", "adjoint_lds")
+    adj_ms = sum(per.get(k, 0.0) for k in adj_parts)
     cand = {"fused_forward": per.get("fused_forward", 0.0), "adjoint": adj_ms}
     dom = max(cand, key=cand.get)
     avg_s = cand[dom] * 1e-3 / max(1.0, launches.get("fused_forward" if dom == "fused_forward"
                                                      else "adjoint_reg", 1.0))
     achieved = alg[dom] / avg_s
-    return {"bound": "alu", "kernel": dom if dom != "adjoint" else "adjoint_reg+adjoint_lds",
+    return {"bound": "alu", "kernel": dom if dom != "adjoint" else "+".join(k for k in adj_parts if k in per),
             "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
             "frac": achieved / PEAK_LANE_OPS, "traffic": None, "avg_launch_ms": avg_s * 1e3,
             "alg_lane_ops_per_launch": alg[dom],
@@ -256,6 +261,15 @@ def main():
         base, acc = cpu_baseline(cfg, d, fit_np, grad_np, st_np, a.cpu_seconds)
         out["cpu_baseline"] = base
         out["accuracy_vs_oracle"] = acc
+    if a.copy_probe_mb:
+        nbytes = a.copy_probe_mb << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
     print(json.dumps(out), flush=True)
 
 

@@ -69,7 +69,7 @@ int adj_span_cap(const Shape& s) {
 }
 
 struct Layout {
-  size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, tune, total;
+  size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, adjl, tune, total;
   int U_stride;
 };
 
@@ -95,6 +95,8 @@ Layout layout_of(const Shape& s) {
   o = align256(o + 64);
   l.gpart = o;
   o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
+  l.adjl = o;  // adjoint tier lists [3][M] and counts [3][M] (per individual in the plain form)
+  o = align256(o + size_t(s.M) * 6 * sizeof(int32_t) + 64);
   l.tune = o;  // outputs of the autotuner's trial calls: fitness, grad, status
   o = align256(o + size_t(s.M) * (std::max(s.C_max, 1) + 2) * sizeof(double));
   l.total = o;
@@ -119,6 +121,7 @@ TuneKey tune_key(const Shape& s, bool grad) {
 }
 struct Tuned {
   int K, R, G;
+  int TC;  // adjoint tier A tape entries (0 for the forward)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuned> g_tuned;  // forward choices
@@ -139,6 +142,7 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   const bool fp64 = (s.flags & GPGOMEA_FP64_NODES) != 0;
   c.K = fp64 ? 4 : 8;
   c.D = fp64 ? 8 : (slots_for(s.L_max) <= 4 ? 4 : 8);
+  c.NP = uop_pairs(s.L_max);
   c.W = 4;
   const int BR = 64 * c.K;
   const int64_t Nr = (s.N + BR - 1) / BR * BR;
@@ -165,43 +169,44 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   return c;
 }
 
-// Adjoint plan.  Register-tape kernel: K rows per lane with a TC-entry tape
-// (K*TC = 64 VGPRs), W = 4 waves, a row tile of at most 32 KB so that several
-// blocks share a CU.  LDS-tape kernel: the largest block that fits its
-// worst-case tape (L_max - 1 entries per wave).  Both use the same spans.
+// Adjoint plan.  Tier A: K rows per lane with a TC-entry register tape,
+// (K, TC) = (4, 16) unless tuned to (2, 16) or (2, 32); W = 4 waves; a
+// row tile of at most 32 KB untuned, so that several blocks share a CU.
+// Tier B: (2, 32) for the tapes between tier A's and 32 entries.  Tier C: the
+// largest LDS-tape block that fits the worst-case tape (L_max - 1 entries per
+// wave).  All tiers use the same spans.
+bool reg_variant(int K, int TC) { return (K == 4 && TC == 16) || (K == 2 && (TC == 16 || TC == 32)); }
+
 AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   AdjPlan a;
   const int Cm = std::max(1, s.C_max);
   const int cap = lds_limit_bytes() - 64;  // static LDS of the kernels
   TileCfg& r = a.reg;
   r.D = D;
+  r.NP = uop_pairs(s.L_max);
   r.W = 4;
-  if (s.L_max <= 63) {
-    r.K = 4;
-    a.reg_tape = 16;
-  } else {
-    r.K = 2;
-    a.reg_tape = 32;
-  }
+  r.K = 4;
+  a.tc_a = 16;
+  a.tc_b = 32;
   a.lane_consts = std::min(Cm, 32);
   r.G = 16;
   r.R = 1024;
   if (t) {
-    if (t->K == 2 || t->K == 4) {
+    if (reg_variant(t->K, t->TC)) {
       r.K = t->K;
-      a.reg_tape = t->K == 4 ? 16 : 32;
+      a.tc_a = t->TC;
     }
     r.R = t->R;
     r.G = t->G;
   }
   const int BRr = 64 * r.K;
-  const size_t tile_cap = t ? size_t(cap) : size_t(32 * 1024);  // untuned: room for 3+ blocks/CU
+  const size_t tile_cap = t ? size_t(cap) : size_t(32 * 1024);
   while (r.R > BRr && (size_t(s.F) * r.R * 4 + size_t(r.R) * 8 > tile_cap ||
                        adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts) > size_t(cap)))
     r.R /= 2;
-  const int64_t Nr = (s.N + BRr - 1) / BRr * BRr;
+  const int64_t Nr = (s.N + 255) / 256 * 256;  // a multiple of every tier's batch
   if (Nr < r.R) r.R = int(Nr);
-  r.R = std::max(BRr, r.R / BRr * BRr);
+  r.R = std::max(256, r.R / 256 * 256);
   r.G = std::max(1, std::min(r.G, s.M));
   r.n_groups = (s.M + r.G - 1) / r.G;
   // spans: enough blocks to fill the chip several times over
@@ -213,12 +218,17 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   a.n_spans = int((s.N + a.span_rows - 1) / a.span_rows);
   r.n_spans = a.n_spans;
 
-  // LDS-tape kernel: its tile must divide span_rows (powers of two <= r.R).
   // A program of L tokens has at most L - 1 tape entries (one per tree edge)
-  // and at most C_max constants, so small shapes never need it.
-  TileCfg& w = a.wide;
+  // and at most C_max constants, so small shapes never reach tier B or C.
   a.tape_cap = std::max(1, s.L_max - 1);
-  a.need_wide = a.tape_cap > a.reg_tape || Cm > a.lane_consts;
+  a.need_b = a.tape_cap > a.tc_a && a.tc_b > a.tc_a;
+  TileCfg& b = a.reg_b;
+  b = r;
+  b.K = 2;
+  a.need_wide = a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts;
+
+  // tier C: its tile must divide span_rows (powers of two <= r.R)
+  TileCfg& w = a.wide;
   w.D = 8;
   bool ok = false;
   const int Ks[2] = {2, 1};
@@ -250,7 +260,7 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
     w.G = 1;
   }
   w.G = std::max(1, std::min(w.G, s.M));
-  w.n_groups = (s.M + w.G - 1) / w.G;
+  w.n_groups = std::min((s.M + w.G - 1) / w.G, 16);  // group slots per span; blocks loop
   w.n_spans = a.n_spans;
   w.tiles_per_span = int(a.span_rows / w.R);
   return a;
@@ -355,14 +365,22 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     if (c.with_grad) {
       const AdjPlan one = plan_adjoint(Shape{1, c.s.L_max, c.s.C_max, c.s.F, c.s.N, c.s.ldx, c.s.flags}, D,
                                        nullptr, adj_span_cap(c.s));
+      int* pcounts = reinterpret_cast<int*>(c.ws + l.adjl);
+      int* list0 = pcounts + 3 * size_t(c.s.M);
+      GG_TIMED("plain_tiers", launch_adjoint_tier_flags(one, meta, ab, c.s.M, pcounts, list0, c.stream));
       for (int i = 0; i < c.s.M; ++i) {
         const uint2* ui = uops + size_t(i) * l.U_stride;
         double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
-        GG_TIMED("plain_adjoint", launch_adjoint_reg(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
-                                                     ab + 2 * size_t(i), gi, c.stream));
+        const double* abi = ab + 2 * size_t(i);
+        const int* ci = pcounts + 3 * size_t(i);
+        GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
+                                                     abi, gi, list0, ci + 0, c.stream));
+        if (one.need_b)
+          GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 1, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
+                                                       stats, abi, gi, list0, ci + 1, c.stream));
         if (one.need_wide)
-          GG_TIMED("plain_adjoint_lds", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
-                                                           stats, ab + 2 * size_t(i), gi, c.stream));
+          GG_TIMED("plain_adjoint", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
+                                                       abi, gi, list0, ci + 2, c.stream));
       }
       GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
                                                      c.s.flags, c.status, c.grad, c.stream));
@@ -374,11 +392,18 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   GG_TIMED("finalize", launch_finalize(meta, c.s.M, part, fc.n_spans, stats, c.s.flags, c.fitness, c.aux,
                                        c.status, ab, c.stream));
   if (c.with_grad) {
-    GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                               gpart, c.stream));
+    int* lists = reinterpret_cast<int*>(c.ws + l.adjl);
+    int* counts = lists + 3 * size_t(c.s.M);
+    const size_t M = size_t(c.s.M);
+    GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, c.stream));
+    GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
+                                               gpart, lists, counts + 0, c.stream));
+    if (ac.need_b)
+      GG_TIMED("adjoint_reg_b", launch_adjoint_reg(ac, 1, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
+                                                   ab, gpart, lists + M, counts + 1, c.stream));
     if (ac.need_wide)
       GG_TIMED("adjoint_lds", launch_adjoint_lds(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                 gpart, c.stream));
+                                                 gpart, lists + 2 * M, counts + 2, c.stream));
     GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab,
                                                    c.s.flags, c.status, c.grad, c.stream));
   }
@@ -408,7 +433,8 @@ int run_call(const Call& c) {
            uintptr_t(c.status), uintptr_t(c.ws), uintptr_t(c.s.M), uintptr_t(c.s.L_max),
            uintptr_t(c.s.C_max), uintptr_t(c.s.F), uintptr_t(c.s.N), uintptr_t(c.s.ldx),
            uintptr_t(c.s.flags), uintptr_t(fc.K), uintptr_t(fc.R), uintptr_t(fc.G),
-           uintptr_t(ac.reg.R), uintptr_t(ac.reg.G), uintptr_t(ac.n_spans)};
+           uintptr_t(ac.reg.R), uintptr_t(ac.reg.G), uintptr_t(ac.reg.K), uintptr_t(ac.tc_a),
+           uintptr_t(ac.n_spans)};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -593,8 +619,8 @@ std::string tune_line(const char* table, const TuneKey& k, const Tuned& t) {
   char b[256];
   std::snprintf(b, sizeof(b),
                 "  {\"table\": \"%s\", \"fp64\": %d, \"Lcls\": %d, \"F\": %d, \"Ncls\": %d, "
-                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d}",
-                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G);
+                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d, \"TC\": %d}",
+                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G, t.TC);
   return b;
 }
 
@@ -626,6 +652,7 @@ bool read_tuning(const char* path, int* n_read) {
           json_int(line, "Mcls", &k.Mcls) && json_int(line, "grad", &k.grad) &&
           json_int(line, "K", &t.K) && json_int(line, "R", &t.R) && json_int(line, "G", &t.G)))
       continue;
+    if (!json_int(line, "TC", &t.TC)) t.TC = 0;
     if (t.K < 1 || t.R < 64 || t.G < 1) continue;
     (fwd ? g_tuned : g_tuned_adj)[k] = t;
     ++n;
@@ -687,7 +714,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   const int Rs_f[5] = {256, 512, 1024, 2048, 4096};
   const int Gs_f[5] = {4, 8, 16, 32, 64};
   const int lds = lds_limit_bytes();
-  Tuned best_f{0, 0, 0};
+  Tuned best_f{0, 0, 0, 0};
   float best_f_ms = 1e30f;
   TileCfg fc_best;
   for (int k : Ks_f) {
@@ -696,7 +723,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
       if (r < 64 * k) continue;
       for (int g : Gs_f) {
         if (forward_lds_bytes(F, r, g) > size_t(lds)) continue;
-        const Tuned t{k, r, g};
+        const Tuned t{k, r, g, 0};
         const TileCfg fc = plan_forward(st, &t);
         const AdjPlan ac = plan_adjoint(st, fc.D, nullptr, adj_span_cap(s));
         const float ms = time_plans(c, fc, ac, trials);
@@ -721,16 +748,16 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   if (with_grad) {
     c.with_grad = true;
     c.grad = grad;
-    const int Ks_a[2] = {4, 2};
+    const int KT_a[3][2] = {{4, 16}, {2, 16}, {2, 32}};
     const int Rs_a[4] = {256, 512, 1024, 2048};
     const int Gs_a[4] = {4, 8, 16, 32};
-    Tuned best_a{0, 0, 0};
+    Tuned best_a{0, 0, 0, 0};
     float best_a_ms = 1e30f;
-    for (int k : Ks_a) {
+    for (const auto& kt : KT_a) {
+      const int k = kt[0];
       for (int r : Rs_a) {
-        if (r < 64 * k) continue;
         for (int g : Gs_a) {
-          const Tuned t{k, r, g};
+          const Tuned t{k, r, g, kt[1]};
           const AdjPlan ac = plan_adjoint(st, fc_best.D, &t, adj_span_cap(s));
           if (ac.reg.R != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
           const float ms = time_plans(c, fc_best, ac, trials);
@@ -748,8 +775,8 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     if (best_a.K) {
       g_tuned_adj[tune_key(s, true)] = best_a;
       len += std::snprintf(desc + len, sizeof(desc) - size_t(len),
-                           "; fitness+gradient with adjoint K=%d R=%d G=%d (%.3f ms)", best_a.K,
-                           best_a.R, best_a.G, double(best_a_ms));
+                           "; fitness+gradient with adjoint K=%d TC=%d R=%d G=%d (%.3f ms)",
+                           best_a.K, best_a.TC, best_a.R, best_a.G, double(best_a_ms));
     }
   }
   if (cache_path) {

@@ -104,6 +104,69 @@ __device__ inline uint2 load_uop(const uint2* __restrict__ prog, int pc) {
   return make_uint2(uint32_t(v), uint32_t(v >> 32));
 }
 
+// Where the interpreter reads its uops from.  Both give the same uop for a
+// wave-uniform pc.
+//
+// UopMem: scalar loads from the uop array (one uop ahead).  Simple, but a
+// scalar load's wait (lgkmcnt) is shared with the LDS row reads and scalar
+// loads return out of order, so every wait for a row also waits for the next
+// uop; used by the kernels where that does not matter.
+struct UopMem {
+  const uint2* __restrict__ p;
+  __device__ inline uint2 at(int pc) const { return load_uop(p, pc); }
+};
+
+// UopRegs<NP>: the whole program held in VGPRs, lane l of register pair e
+// holding uop e*64 + l (NP*64 >= uops of the longest program); at() copies a
+// uop into SGPRs with v_readlane, so the interpreter loop touches no memory
+// for its instruction stream.  load() is a coalesced vector load (vmcnt, not
+// lgkmcnt), issued one individual ahead.
+template <int NP>
+struct UopRegs {
+  uint32_t lo[NP], hi[NP];
+  __device__ inline void load(const uint2* __restrict__ prog, int n) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int e = 0; e < NP; ++e) {
+      const int idx = e * 64 + lane;
+      uint2 u = make_uint2(uint32_t(UOP_END), 0u);
+      if (idx < n) u = prog[idx];
+      lo[e] = u.x;
+      hi[e] = u.y;
+    }
+  }
+  __device__ inline uint2 at(int pc) const {
+    const int l = pc & 63;
+    if constexpr (NP == 1) {
+      return make_uint2(uint32_t(__builtin_amdgcn_readlane(int(lo[0]), l)),
+                        uint32_t(__builtin_amdgcn_readlane(int(hi[0]), l)));
+    } else {
+      const int q = pc >> 6;
+      uint32_t a = uint32_t(UOP_END), b = 0u;
+#pragma unroll
+      for (int e = 0; e < NP; ++e) {
+        if (q == e) {
+          a = uint32_t(__builtin_amdgcn_readlane(int(lo[e]), l));
+          b = uint32_t(__builtin_amdgcn_readlane(int(hi[e]), l));
+          GG_BRANCH();
+        }
+      }
+      return make_uint2(a, b);
+    }
+  }
+};
+
+// Dynamic work queue of one block and one row tile: every wave claims the
+// next index from an LDS counter (one atomic by lane 0; the value is made
+// wave-uniform with readfirstlane, so loops on it exit with a scalar branch),
+// which keeps the waves of a block busy until the tile's barrier however
+// unequal the programs are.  The counter must be reset before the tile.
+__device__ inline int claim_next(int* ctr) {
+  int t = 0;
+  if ((threadIdx.x & 63) == 0) t = atomicAdd(ctr, 1);
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
 // Per-element application of the protected operators to K-vectors.
 template <typename T, int K>
 struct VOps {
@@ -139,11 +202,11 @@ struct VOps {
 };
 
 // Evaluate the program on K rows per lane; returns the predictions.
-//   prog    uop stream of this individual (wave-uniform pointer)
+//   prog    uop source of this individual (UopMem or UopRegs)
 //   xt      LDS row tile: feature k, row r at xt[k*rstride + r]
 //   lrow    this lane's first row within the tile (multiple of K)
-template <typename T, int K, int D>
-__device__ inline typename VecT<T, K>::type run_program(const uint2* __restrict__ prog,
+template <typename T, int K, int D, class Src>
+__device__ inline typename VecT<T, K>::type run_program(const Src& prog,
                                                         const float* __restrict__ xt, int rstride,
                                                         int lrow) {
   using V = typename VecT<T, K>::type;
@@ -151,11 +214,11 @@ __device__ inline typename VecT<T, K>::type run_program(const uint2* __restrict_
   Slots<V, D> st;
   V acc = T(0), t = T(0);
   const float* __restrict__ xl = xt + lrow;
-  uint2 cur = load_uop(prog, 0);
+  uint2 cur = prog.at(0);
   int pc = 0;
 #pragma unroll 1
   for (;;) {
-    const uint2 nxt = load_uop(prog, pc + 1);
+    const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
     const uint32_t op = uop_op(h);
     if (op == UOP_END) break;

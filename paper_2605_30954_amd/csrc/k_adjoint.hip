@@ -13,19 +13,22 @@
 // uops backwards.  A tree node has exactly one parent, so adjoints never
 // accumulate except at constants.
 //
-// Two kernels share this code and split the individuals between them:
-//  * k_adj_reg (most individuals): the tape is a register array of TC entries
-//    addressed by a wave-uniform index (indirect VGPR addressing, no LDS), and
-//    every lane sums its own rows' constant adjoints in an LDS column (binary32
-//    over the R/64 rows of one tile); once per (tile, individual) the wave
-//    adds the 64 columns in binary64.  LDS then holds only the row tile, so
+// The individuals are split into tiers by the size of their tape (the
+// partials the reverse sweep needs) and their constant count; a partition
+// kernel writes one list per tier after the forward pass, and one kernel per
+// tier walks its own list:
+//  * k_adj_reg, tier A and tier B: the tape is a register array of TC entries
+//    per row addressed by a wave-uniform index (indirect VGPR addressing, no
+//    LDS); tier A uses a small tape (most programs), tier B TC = 32.  Every
+//    lane sums its own rows' constant adjoints in an LDS column (binary32 over
+//    the R/64 rows of one tile); once per (tile, individual) the wave adds the
+//    64 columns in binary64.  LDS holds little more than the row tile, so
 //    several blocks share a CU.
-//  * k_adj_lds (individuals whose tape exceeds TC entries or whose constants
-//    exceed the column count): the tape lives in wave-private LDS and every
-//    constant adjoint is reduced across the wave (binary64) per batch.
-// A block writes the partials of the individuals it processed; both kernels
-// cut the rows into the same spans, so every (individual, span) partial is
-// written by exactly one of them.
+//  * k_adj_lds, tier C (longer tapes, or more constants than columns): the
+//    tape lives in wave-private LDS; all waves of a block share one individual
+//    and reduce its constant adjoints across the wave (binary64) per batch.
+// Every kernel cuts the rows into the same spans, so every (individual, span)
+// partial is written exactly once.
 #include <hip/hip_runtime.h>
 
 #include "interp.h"
@@ -46,19 +49,70 @@ struct AdjParams {
   const double* stats;
   const double* ab;
   double* gpart;      // [M][n_spans][C_max]
+  const int* list;    // this tier's individuals, in batch order
+  const int* count;   // their number
   int R, G, n_groups, n_spans;
-  int64_t span_rows;  // rows per span (common to both kernels)
-  int tape_cap;       // LDS tape entries per wave (k_adj_lds)
-  int reg_tape;       // TC: register tape entries (k_adj_reg)
-  int lane_consts;    // CC: constant columns per wave (k_adj_reg)
+  int64_t span_rows;  // rows per span (common to every tier)
+  int tape_cap;       // LDS tape entries per wave (tier C)
+  int lane_consts;    // CC: constant columns per wave (register tiers)
 };
 
-// Which kernel owns individual i (both evaluate the same predicate).
-__device__ inline bool adj_active(const ProgMeta& pm, double s1) {
-  return pm.status == 0 && s1 != 0.0 && pm.n_const > 0;
+// Tier of an individual: -1 no gradient work (bad program, non-finite, b = 0
+// or no constant), 0 register tape A, 1 register tape B, 2 LDS tape.
+__device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, int CC) {
+  if (pm.status != 0 || s1 == 0.0 || pm.n_const <= 0) return -1;
+  if (pm.n_const <= CC && pm.n_tape <= tcA) return 0;
+  if (pm.n_const <= CC && pm.n_tape <= tcB) return 1;
+  return 2;
 }
-__device__ inline bool adj_fits_reg(const ProgMeta& pm, int TC, int CC) {
-  return pm.n_tape <= TC && pm.n_const <= CC;
+
+// One block: thread t classifies a contiguous chunk of individuals; a
+// block-wide scan of the per-thread counts gives each chunk its offsets, so
+// the lists keep batch order (deterministic).
+constexpr int kPartThreads = 1024;
+__global__ __launch_bounds__(kPartThreads) void k_adj_partition(
+    const ProgMeta* __restrict__ meta, const double* __restrict__ ab, int M, int tcA, int tcB,
+    int CC, int* __restrict__ lists, int* __restrict__ counts) {
+  __shared__ int sc[3][kPartThreads];
+  const int t = threadIdx.x;
+  const int chunk = (M + kPartThreads - 1) / kPartThreads;
+  const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
+  int n0 = 0, n1 = 0, n2 = 0;
+  for (int i = lo; i < hi; ++i) {
+    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC);
+    n0 += k == 0;
+    n1 += k == 1;
+    n2 += k == 2;
+  }
+  sc[0][t] = n0;
+  sc[1][t] = n1;
+  sc[2][t] = n2;
+  __syncthreads();
+  for (int o = 1; o < kPartThreads; o <<= 1) {  // inclusive Hillis-Steele scan
+    int a0 = 0, a1 = 0, a2 = 0;
+    if (t >= o) {
+      a0 = sc[0][t - o];
+      a1 = sc[1][t - o];
+      a2 = sc[2][t - o];
+    }
+    __syncthreads();
+    sc[0][t] += a0;
+    sc[1][t] += a1;
+    sc[2][t] += a2;
+    __syncthreads();
+  }
+  int w0 = sc[0][t] - n0, w1 = sc[1][t] - n1, w2 = sc[2][t] - n2;  // exclusive offsets
+  for (int i = lo; i < hi; ++i) {
+    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC);
+    if (k == 0) lists[w0++] = i;
+    if (k == 1) lists[M + w1++] = i;
+    if (k == 2) lists[2 * M + w2++] = i;
+  }
+  if (t == kPartThreads - 1) {
+    counts[0] = sc[0][t];
+    counts[1] = sc[1][t];
+    counts[2] = sc[2][t];
+  }
 }
 
 // Wave-private tape in LDS: entry e, lane l at base[(e*64 + l)*K].
@@ -122,21 +176,20 @@ struct RegTape {
 // Forward sweep with the tape (float nodes).  Same values as run_program; in
 // addition each uop stores d(result)/d(acc operand) and d(result)/d(src
 // operand) when the reverse sweep needs them (tape_acc / tape_src).
-template <int K, int D, class Tape>
+template <int K, int D, class Src, class Tape>
 __device__ inline typename VecT<float, K>::type run_forward_taped(
-    const uint2* __restrict__ prog, const float* __restrict__ xt, int rstride, int lrow,
-    Tape& tape) {
+    const Src& prog, const float* __restrict__ xt, int rstride, int lrow, Tape& tape) {
   using V = typename VecT<float, K>::type;
   using P = Prot<float>;
   using Dv = Deriv<float>;
   Slots<V, D> st;
   V acc = 0.0f, t = 0.0f, fa = 1.0f, fs = 1.0f;
   const float* __restrict__ xl = xt + lrow;
-  uint2 cur = load_uop(prog, 0);
+  uint2 cur = prog.at(0);
   int pc = 0, tp = 0;
 #pragma unroll 1
   for (;;) {
-    const uint2 nxt = load_uop(prog, pc + 1);
+    const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
     const uint32_t op = uop_op(h);
     if (op == UOP_END) break;
@@ -225,19 +278,19 @@ struct LaneSink {
 
 // Reverse sweep.  g = adjoint of the program output per row (zero on padding
 // rows); kv = valid rows of this lane.
-template <int K, int D, class Tape, class Sink>
-__device__ inline void run_reverse(const uint2* __restrict__ prog, int n_uops, int n_tape,
+template <int K, int D, class Src, class Tape, class Sink>
+__device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
                                    typename VecT<float, K>::type g, const Tape& tape, Sink& sink,
                                    int kv) {
   using V = typename VecT<float, K>::type;
   Slots<V, D> gs;  // adjoints of pushed subtrees
   V gsrc = 0.0f;
   int tp = n_tape;
-  uint2 nxt = load_uop(prog, n_uops >= 2 ? n_uops - 2 : 0);
+  uint2 nxt = prog.at(n_uops >= 2 ? n_uops - 2 : 0);
 #pragma unroll 1
   for (int pc = n_uops - 2; pc >= 0; --pc) {
     const uint2 u = nxt;
-    nxt = load_uop(prog, pc > 0 ? pc - 1 : 0);
+    nxt = prog.at(pc > 0 ? pc - 1 : 0);
     const uint32_t h = u.x;
     const uint32_t op = uop_op(h);
     const uint32_t sk = uop_src(h);
@@ -261,20 +314,20 @@ __device__ inline void run_reverse(const uint2* __restrict__ prog, int n_uops, i
   }
 }
 
-// Block prologue shared by both kernels: the (span, group) of this block with
-// the same XCD-aware numbering as the forward kernel (consecutive items, which
-// share a span and so the same rows of X, land on one XCD and its L2).
+// Block prologue shared by the tier kernels: the (span, group slot) of this
+// block with the same XCD-aware numbering as the forward kernel (consecutive
+// items, which share a span and so the same rows of X, land on one XCD and
+// its L2).  A block takes groups slot, slot + n_groups, ... of its tier's list.
 struct AdjItem {
-  int span, ind0, Gn;
+  int span, slot;
 };
 __device__ inline AdjItem adj_item(const AdjParams& p) {
   const int total = p.n_spans * p.n_groups;
   const int b0 = blockIdx.x;
   const int x = b0 & 7, kk = b0 >> 3, q = total >> 3, r8 = total & 7;
   const int item = x * q + (x < r8 ? x : r8) + kk;
-  const int span = item / p.n_groups, grp = item - span * p.n_groups;
-  const int ind0 = grp * p.G;
-  return {span, ind0, min(p.G, p.M - ind0)};
+  const int span = item / p.n_groups;
+  return {span, item - span * p.n_groups};
 }
 
 // Stage one row tile of X (feature-major, zero past the last row) and the
@@ -305,110 +358,110 @@ __device__ inline typename VecT<float, K>::type adj_seed(const typename VecT<flo
   return g;
 }
 
-// Write this block's partials of the individuals `mine` selects.
-template <class Pred>
-__device__ inline void adj_write(const AdjParams& p, const AdjItem& it, const double* gacc, Pred mine) {
-  for (int j = threadIdx.x; j < it.Gn * p.C_max; j += blockDim.x) {
+// Write the partials of this group (individuals list[base .. base+Gn)).
+__device__ inline void adj_write(const AdjParams& p, int span, int base, int Gn, const double* gacc) {
+  for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) {
     const int jj = j / p.C_max, c = j - jj * p.C_max;
-    const int i = it.ind0 + jj;
-    if (mine(i)) p.gpart[(size_t(i) * p.n_spans + it.span) * p.C_max + c] = gacc[j];
+    const int i = p.list[base + jj];
+    p.gpart[(size_t(i) * p.n_spans + span) * p.C_max + c] = gacc[j];
   }
 }
 
-template <int K, int D, int W, int TC>
+template <int K, int D, int W, int TC, int NP>
 __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R = p.R;
   const int CC = p.lane_consts;
   float* xs = reinterpret_cast<float*>(smem_raw);
   double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
-  double* gacc = yts + R;                                    // G * C_max
+  double* gacc = yts + R;                                                     // G * C_max
   float* lacc_all = reinterpret_cast<float*>(gacc + size_t(p.G) * p.C_max);  // W * CC * 65
 
   const AdjItem it = adj_item(p);
+  const int cnt = __builtin_amdgcn_readfirstlane(*p.count);
+  if (it.slot * p.G >= cnt) return;  // whole block: nothing of this tier here
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
   constexpr int BR = 64 * K;
   float* lacc = lacc_all + size_t(wv) * CC * kColStride;
   LaneSink sink{lacc + lane};
-
-  for (int j = threadIdx.x; j < it.Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
   const int64_t s_begin = int64_t(it.span) * p.span_rows;
   const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
-  for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
-    const int nvalid = int(min<int64_t>(R, s_end - r0));
-    __syncthreads();
-    adj_stage(p, xs, yts, r0, nvalid, ybar);
-    __syncthreads();
-    const int nbatch = (nvalid + BR - 1) / BR;
-    for (int jj = wv; jj < it.Gn; jj += W) {  // wave-uniform trip count
-      const int i = it.ind0 + jj;
-      const ProgMeta pm = p.meta[i];
-      const double s1 = p.ab[size_t(i) * 2 + 1];
-      const int skip = !adj_active(pm, s1) || !adj_fits_reg(pm, TC, CC);
-      if (__builtin_amdgcn_readfirstlane(skip)) continue;
-      const int nc = __builtin_amdgcn_readfirstlane(pm.n_const);
-      const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
-      const uint2* prog = p.uops + size_t(i) * p.U_stride;
-      for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
-      for (int b = 0; b < nbatch; ++b) {
-        const int lrow = b * BR + lane * K;
-        RegTape<K, TC> tape;
-        const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
-        const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-        const int kv = max(0, min(K, nvalid - lrow));
-        run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
-      }
-      // the wave's column writes must land before lane c reads column c
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (lane < nc) {
-        const float* colc = lacc + lane * kColStride;
-        double s0 = 0.0, s1r = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 4
-        for (int k = 0; k < 64; k += 4) {
-          s0 += double(colc[k]);
-          s1r += double(colc[k + 1]);
-          s2 += double(colc[k + 2]);
-          s3 += double(colc[k + 3]);
+
+  __shared__ int queue;
+  for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {  // block-uniform
+    const int base = grp * p.G;
+    const int Gn = min(p.G, cnt - base);
+    __syncthreads();  // previous group's partials written
+    for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
+    for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
+      const int nvalid = int(min<int64_t>(R, s_end - r0));
+      __syncthreads();
+      if (threadIdx.x == 0) queue = 0;
+      adj_stage(p, xs, yts, r0, nvalid, ybar);
+      __syncthreads();
+      const int nbatch = (nvalid + BR - 1) / BR;
+      // the waves claim the group's individuals from the tile's queue; the
+      // next one is claimed and its program loaded while this one runs
+      UopRegs<NP> prog, prog_next;
+      int jj = claim_next(&queue);
+      if (jj < Gn) prog.load(p.uops + size_t(p.list[base + jj]) * p.U_stride, p.U_stride);
+      while (jj < Gn) {  // wave-uniform
+        const int i = __builtin_amdgcn_readfirstlane(p.list[base + jj]);
+        const int jn = claim_next(&queue);
+        if (jn < Gn) prog_next.load(p.uops + size_t(p.list[base + jn]) * p.U_stride, p.U_stride);
+        const ProgMeta pm = p.meta[i];
+        const int nc = __builtin_amdgcn_readfirstlane(pm.n_const);
+        const double s1 = p.ab[size_t(i) * 2 + 1];
+        const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
+        for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
+        for (int b = 0; b < nbatch; ++b) {
+          const int lrow = b * BR + lane * K;
+          RegTape<K, TC> tape;
+          const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
+          const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
+          const int kv = max(0, min(K, nvalid - lrow));
+          run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
         }
-        gacc[size_t(jj) * p.C_max + lane] += (s0 + s1r) + (s2 + s3);
+        // the wave's column writes must land before lane c reads column c
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < nc) {
+          const float* colc = lacc + lane * kColStride;
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+          for (int k = 0; k < 64; k += 4) {
+            a0 += double(colc[k]);
+            a1 += double(colc[k + 1]);
+            a2 += double(colc[k + 2]);
+            a3 += double(colc[k + 3]);
+          }
+          gacc[size_t(jj) * p.C_max + lane] += (a0 + a1) + (a2 + a3);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        prog = prog_next;
+        jj = jn;
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    __syncthreads();
+    adj_write(p, it.span, base, Gn, gacc);
   }
-  __syncthreads();
-  adj_write(p, it, gacc, [&](int i) {
-    const ProgMeta pm = p.meta[i];
-    return adj_active(pm, p.ab[size_t(i) * 2 + 1]) && adj_fits_reg(pm, TC, CC);
-  });
 }
 
-// LDS-tape kernel: only the individuals the register kernel cannot take.
-// They are rare, so all W waves share each one: wave w takes batches w, w+W,
-// ... of a tile and adds its constant adjoints to its own copy of the
-// accumulators; the copies are summed in wave order at the end (bitwise
-// repeatable).  A block whose group holds none of them exits at once.
+// Tier C: all W waves share each individual (wave w takes batches w, w+W, ...
+// of a tile and adds to its own copy of the accumulators; the copies are
+// summed in wave order: bitwise repeatable).
 template <int K, int D, int W>
 __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R = p.R;
-  const int TC = p.reg_tape, CC = p.lane_consts;
-  __shared__ int any;
   const AdjItem it = adj_item(p);
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  if (int(threadIdx.x) < it.Gn) {
-    const int i = it.ind0 + threadIdx.x;
-    const ProgMeta pm = p.meta[i];
-    if (adj_active(pm, p.ab[size_t(i) * 2 + 1]) && !adj_fits_reg(pm, TC, CC)) any = 1;
-  }
-  __syncthreads();
-  if (any == 0) return;
+  const int cnt = __builtin_amdgcn_readfirstlane(*p.count);
+  if (it.slot * p.G >= cnt) return;
 
   float* xs = reinterpret_cast<float*>(smem_raw);
   double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
@@ -423,114 +476,176 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
   constexpr int BR = 64 * K;
   LdsTape<K> tape{tape_all + size_t(wv) * p.tape_cap * 64 * K, lane};
   const int GC = p.G * p.C_max;
-
-  for (int j = threadIdx.x; j < W * GC; j += blockDim.x) gacc[j] = 0.0;
   const int64_t s_begin = int64_t(it.span) * p.span_rows;
   const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
-  for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
-    const int nvalid = int(min<int64_t>(R, s_end - r0));
+
+  for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {
+    const int base = grp * p.G;
+    const int Gn = min(p.G, cnt - base);
     __syncthreads();
-    adj_stage(p, xs, yts, r0, nvalid, ybar);
-    __syncthreads();
-    const int nbatch = (nvalid + BR - 1) / BR;
-    for (int jj = 0; jj < it.Gn; ++jj) {  // uniform over the block
-      const int i = it.ind0 + jj;
-      const ProgMeta pm = p.meta[i];
-      const double s1 = p.ab[size_t(i) * 2 + 1];
-      const int skip = !adj_active(pm, s1) || adj_fits_reg(pm, TC, CC) || pm.n_tape > p.tape_cap;
-      if (__builtin_amdgcn_readfirstlane(skip)) continue;
-      const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
-      const uint2* prog = p.uops + size_t(i) * p.U_stride;
-      WaveSink sink{gacc + size_t(wv) * GC + size_t(jj) * p.C_max};
-      for (int b = wv; b < nbatch; b += W) {
-        const int lrow = b * BR + lane * K;
-        const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
-        const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-        const int kv = max(0, min(K, nvalid - lrow));
-        run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
+    for (int j = threadIdx.x; j < W * GC; j += blockDim.x) gacc[j] = 0.0;
+    for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
+      const int nvalid = int(min<int64_t>(R, s_end - r0));
+      __syncthreads();
+      adj_stage(p, xs, yts, r0, nvalid, ybar);
+      __syncthreads();
+      const int nbatch = (nvalid + BR - 1) / BR;
+      for (int jj = 0; jj < Gn; ++jj) {  // uniform over the block
+        const int i = __builtin_amdgcn_readfirstlane(p.list[base + jj]);
+        const ProgMeta pm = p.meta[i];
+        if (__builtin_amdgcn_readfirstlane(pm.n_tape) > p.tape_cap) continue;  // cannot happen
+        const double s1 = p.ab[size_t(i) * 2 + 1];
+        const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
+        const UopMem prog{p.uops + size_t(i) * p.U_stride};
+        WaveSink sink{gacc + size_t(wv) * GC + size_t(jj) * p.C_max};
+        for (int b = wv; b < nbatch; b += W) {
+          const int lrow = b * BR + lane * K;
+          const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
+          const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
+          const int kv = max(0, min(K, nvalid - lrow));
+          run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
+        }
       }
     }
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < GC; j += blockDim.x) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < GC; j += blockDim.x) {
 #pragma unroll
-    for (int w = 1; w < W; ++w) gacc[j] += gacc[size_t(w) * GC + j];
+      for (int w = 1; w < W; ++w) gacc[j] += gacc[size_t(w) * GC + j];
+    }
+    adj_write(p, it.span, base, Gn, gacc);  // each thread reads what it summed
   }
-  adj_write(p, it, gacc, [&](int i) {
-    const ProgMeta pm = p.meta[i];
-    return adj_active(pm, p.ab[size_t(i) * 2 + 1]) && !adj_fits_reg(pm, TC, CC);
-  });
 }
 
-template <int K, int D, int W, int TC>
-static hipError_t reg_impl(const AdjPlan& a, const AdjParams& ap, hipStream_t s) {
-  const size_t sh = adjoint_reg_lds_bytes(ap.F, a.reg.R, a.reg.G, ap.C_max, W, a.lane_consts);
-  const int nb = a.n_spans * a.reg.n_groups;
-  hipLaunchKernelGGL((k_adj_reg<K, D, W, TC>), dim3(nb), dim3(W * 64), sh, s, ap);
+template <int K, int D, int W, int TC, int NP>
+static hipError_t reg_impl1(const TileCfg& c, int CC, const AdjParams& ap, hipStream_t s) {
+  const size_t sh = adjoint_reg_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, CC);
+  hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP>), dim3(ap.n_spans * ap.n_groups), dim3(W * 64), sh, s,
+                     ap);
   return hipGetLastError();
+}
+
+// programs of up to 63 tokens use D = 4 (one register pair); longer ones D = 8
+template <int K, int D, int W, int TC>
+static hipError_t reg_impl(const TileCfg& c, int CC, const AdjParams& ap, hipStream_t s) {
+  if constexpr (D == 4) {
+    if (c.NP != 1) return hipErrorInvalidValue;
+    return reg_impl1<K, 4, W, TC, 1>(c, CC, ap, s);
+  } else {
+    switch (c.NP) {
+      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, ap, s);
+      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, ap, s);
+      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, ap, s);
+      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, ap, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
 }
 
 template <int K, int D, int W>
-static hipError_t lds_impl(const AdjPlan& a, const AdjParams& ap, hipStream_t s) {
-  const size_t sh = adjoint_lds_bytes(ap.F, a.wide.R, a.wide.G, ap.C_max, W, K, ap.tape_cap);
-  const int nb = a.n_spans * a.wide.n_groups;
-  hipLaunchKernelGGL((k_adj_lds<K, D, W>), dim3(nb), dim3(W * 64), sh, s, ap);
+static hipError_t lds_impl(const TileCfg& c, const AdjParams& ap, hipStream_t s) {
+  const size_t sh = adjoint_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, K, ap.tape_cap);
+  hipLaunchKernelGGL((k_adj_lds<K, D, W>), dim3(ap.n_spans * ap.n_groups), dim3(W * 64), sh, s, ap);
   return hipGetLastError();
 }
 
-static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, const uint2* uops, int U_stride,
-                            const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                            const double* stats, const double* ab, double* gpart) {
+static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, const uint2* uops,
+                            int U_stride, const ProgMeta* meta, int M, int C_max,
+                            const DataArgs& d, const double* stats, const double* ab,
+                            double* gpart, const int* list, const int* count) {
   return AdjParams{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
-                   c.R, c.G, c.n_groups, a.n_spans, a.span_rows, a.tape_cap, a.reg_tape,
+                   list, count, c.R, c.G, n_groups, a.n_spans, a.span_rows, a.tape_cap,
                    a.lane_consts};
 }
 
-hipError_t launch_adjoint_reg(const AdjPlan& a, const uint2* uops, int U_stride,
+hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
+                                    int* lists, int* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_partition, dim3(1), dim3(kPartThreads), 0, s, meta, ab, M, a.tc_a,
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, lists, counts);
+  return hipGetLastError();
+}
+
+// Plain form: per individual i, counts[3i + k] = 1 if it is in tier k, else
+// 0, and list0[0] = 0 (each per-individual launch lists its one individual).
+__global__ __launch_bounds__(256) void k_adj_tier_flags(const ProgMeta* __restrict__ meta,
+                                                        const double* __restrict__ ab, int M,
+                                                        int tcA, int tcB, int CC,
+                                                        int* __restrict__ counts,
+                                                        int* __restrict__ list0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) list0[0] = 0;
+  if (i >= M) return;
+  const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC);
+  counts[3 * i + 0] = k == 0;
+  counts[3 * i + 1] = k == 1;
+  counts[3 * i + 2] = k == 2;
+}
+
+hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
+                                     int* counts, int* list0, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_tier_flags, dim3((M + 255) / 256), dim3(256), 0, s, meta, ab, M, a.tc_a,
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, counts, list0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                              const double* stats, const double* ab, double* gpart, hipStream_t s) {
-  const AdjParams ap = adj_params(a, a.reg, uops, U_stride, meta, M, C_max, d, stats, ab, gpart);
-  const TileCfg& r = a.reg;
-  if (r.W != 4) return hipErrorInvalidValue;
-  if (r.K == 4 && a.reg_tape == 16 && r.D == 4) return reg_impl<4, 4, 4, 16>(a, ap, s);
-  if (r.K == 4 && a.reg_tape == 16 && r.D == 8) return reg_impl<4, 8, 4, 16>(a, ap, s);
-  if (r.K == 2 && a.reg_tape == 32 && r.D == 4) return reg_impl<2, 4, 4, 32>(a, ap, s);
-  if (r.K == 2 && a.reg_tape == 32 && r.D == 8) return reg_impl<2, 8, 4, 32>(a, ap, s);
+                              const double* stats, const double* ab, double* gpart,
+                              const int* list, const int* count, hipStream_t s) {
+  const TileCfg& c = tier == 0 ? a.reg : a.reg_b;
+  const int TC = tier == 0 ? a.tc_a : a.tc_b;
+  const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
+                                  gpart, list, count);
+  const int CC = a.lane_consts;
+  if (c.W != 4) return hipErrorInvalidValue;
+  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                              const double* stats, const double* ab, double* gpart, hipStream_t s) {
-  const AdjParams ap = adj_params(a, a.wide, uops, U_stride, meta, M, C_max, d, stats, ab, gpart);
+                              const double* stats, const double* ab, double* gpart,
+                              const int* list, const int* count, hipStream_t s) {
   const TileCfg& w = a.wide;
+  const AdjParams ap = adj_params(a, w, w.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
+                                  gpart, list, count);
   if (w.D != 8) return hipErrorInvalidValue;
-  if (w.K == 2 && w.W == 4) return lds_impl<2, 8, 4>(a, ap, s);
-  if (w.K == 2 && w.W == 2) return lds_impl<2, 8, 2>(a, ap, s);
-  if (w.K == 2 && w.W == 1) return lds_impl<2, 8, 1>(a, ap, s);
-  if (w.K == 1 && w.W == 4) return lds_impl<1, 8, 4>(a, ap, s);
-  if (w.K == 1 && w.W == 2) return lds_impl<1, 8, 2>(a, ap, s);
-  if (w.K == 1 && w.W == 1) return lds_impl<1, 8, 1>(a, ap, s);
+  if (w.K == 2 && w.W == 4) return lds_impl<2, 8, 4>(w, ap, s);
+  if (w.K == 2 && w.W == 2) return lds_impl<2, 8, 2>(w, ap, s);
+  if (w.K == 2 && w.W == 1) return lds_impl<2, 8, 1>(w, ap, s);
+  if (w.K == 1 && w.W == 4) return lds_impl<1, 8, 4>(w, ap, s);
+  if (w.K == 1 && w.W == 2) return lds_impl<1, 8, 2>(w, ap, s);
+  if (w.K == 1 && w.W == 1) return lds_impl<1, 8, 1>(w, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 
+// One wave per (individual, constant): lane l sums spans l, l+64, ... in
+// order, then a fixed xor-tree over the wave.
 __global__ __launch_bounds__(256) void k_grad_finalize(const ProgMeta* __restrict__ meta, int M,
                                                        int C_max, const double* __restrict__ gpart,
                                                        int n_spans, const double* __restrict__ stats,
                                                        const double* __restrict__ ab,
                                                        double* __restrict__ grad) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(M) * C_max) return;
+  const int64_t idx = __builtin_amdgcn_readfirstlane(
+      int(int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (idx >= int64_t(M) * C_max) return;  // whole wave
+  const int lane = threadIdx.x & 63;
   const int i = int(idx / C_max), j = int(idx - int64_t(i) * C_max);
   const ProgMeta pm = meta[i];
-  double g = 0.0;
   const double s1 = ab[size_t(i) * 2 + 1];
-  if (pm.status == 0 && j < pm.n_const && s1 != 0.0) {
+  const bool live = pm.status == 0 && j < pm.n_const && s1 != 0.0;
+  double g = 0.0;
+  if (live) {
     const double* q = gpart + size_t(i) * n_spans * C_max + j;
-    for (int s = 0; s < n_spans; ++s) g += q[size_t(s) * C_max];
-    g *= 2.0 * s1 / stats[ST_N];
+    for (int s = lane; s < n_spans; s += 64) g += q[size_t(s) * C_max];
   }
-  grad[idx] = g;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+  if (lane == 0) grad[idx] = live ? g * (2.0 * s1 / stats[ST_N]) : 0.0;
 }
 
 hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const double* gpart,
@@ -539,8 +654,8 @@ hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const do
                                 hipStream_t s) {
   (void)flags;
   (void)status;
-  const int64_t n = int64_t(M) * C_max;
-  hipLaunchKernelGGL(k_grad_finalize, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, meta, M,
+  const int64_t n = int64_t(M) * C_max;  // one wave each, 4 per block
+  hipLaunchKernelGGL(k_grad_finalize, dim3(unsigned((n + 3) / 4)), dim3(256), 0, s, meta, M,
                      C_max, gpart, n_spans, stats, ab, grad);
   return hipGetLastError();
 }

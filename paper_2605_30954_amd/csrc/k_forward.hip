@@ -98,7 +98,7 @@ __device__ inline int xcd_item(int b, int total) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <typename T, int K, int D, int W, bool SSE>
+template <typename T, int K, int D, int W, bool SSE, int NP>
 __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R = p.R;
@@ -111,11 +111,11 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   const int span = item / p.n_groups, grp = item - span * p.n_groups;
   const int ind0 = grp * p.G;
   const int Gn = min(p.G, p.M - ind0);
-  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
   constexpr int BR = 64 * K;  // rows per batch
 
+  __shared__ int queue;
   for (int j = threadIdx.x; j < Gn * 4; j += blockDim.x) accs[j] = 0.0;
 
   const int64_t span_r0 = int64_t(span) * p.tiles_per_span * R;
@@ -124,33 +124,42 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     if (r0 >= p.N) break;
     const int nvalid = int(min<int64_t>(R, p.N - r0));
     __syncthreads();  // previous tile fully consumed
+    if (threadIdx.x == 0) queue = 0;
     stage_tile(xs, p.X, p.ldx, p.F, R, r0, nvalid);
     for (int r = threadIdx.x; r < R; r += blockDim.x)
       yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
-    // wave w takes individuals w, w+W, ... of the group: a wave-uniform loop
-    // with no divergent branch and no cross-lane traffic inside it
-    for (int jj = wv; jj < Gn; jj += W) {
+    // the waves claim the group's individuals from the tile's queue (a
+    // wave-uniform loop, no cross-lane traffic under divergent control); the
+    // next individual is claimed and its program loaded while this one runs
+    UopRegs<NP> prog, prog_next;
+    int jj = claim_next(&queue);
+    if (jj < Gn) prog.load(p.uops + size_t(ind0 + jj) * p.U_stride, p.U_stride);
+    while (jj < Gn) {
       const int i = ind0 + jj;
-      if (__builtin_amdgcn_readfirstlane(p.meta[i].status) != 0) continue;
-      const uint2* prog = p.uops + size_t(i) * p.U_stride;
-      const double mu = double(p.meta[i].mu);
-      const double emu = mu - ybar;
-      Moments<SSE> m;
-      for (int b = 0; b < nbatch; ++b) {
-        const int lrow = b * BR + lane * K;
-        const auto v = run_program<T, K, D>(prog, xs, R, lrow);
-        accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
+      const int jn = claim_next(&queue);
+      if (jn < Gn) prog_next.load(p.uops + size_t(ind0 + jn) * p.U_stride, p.U_stride);
+      if (__builtin_amdgcn_readfirstlane(p.meta[i].status) == 0) {
+        const double mu = double(p.meta[i].mu);
+        const double emu = mu - ybar;
+        Moments<SSE> m;
+        for (int b = 0; b < nbatch; ++b) {
+          const int lrow = b * BR + lane * K;
+          const auto v = run_program<T, K, D>(prog, xs, R, lrow);
+          accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
+        }
+        const double sa = wave_sum(m.a), sb = wave_sum(m.b), sc = wave_sum(m.c);
+        const double se = SSE ? wave_sum(m.e) : 0.0;
+        // every lane holds the same totals: all lanes store the same value (no
+        // divergent branch between the cross-lane sums of consecutive individuals)
+        accs[jj * 4 + 0] += sa;
+        accs[jj * 4 + 1] += sb;
+        accs[jj * 4 + 2] += sc;
+        accs[jj * 4 + 3] += se;
       }
-      const double sa = wave_sum(m.a), sb = wave_sum(m.b), sc = wave_sum(m.c);
-      const double se = SSE ? wave_sum(m.e) : 0.0;
-      // every lane holds the same totals: all lanes store the same value (no
-      // divergent branch between the cross-lane sums of consecutive individuals)
-      accs[jj * 4 + 0] += sa;
-      accs[jj * 4 + 1] += sb;
-      accs[jj * 4 + 2] += sc;
-      accs[jj * 4 + 3] += se;
+      prog = prog_next;
+      jj = jn;
     }
   }
   __syncthreads();
@@ -160,16 +169,27 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   }
 }
 
-template <typename T, int K, int D, int W>
+template <typename T, int K, int D, int W, int NP>
 static hipError_t fused_impl(const TileCfg& c, const FwdParams& fp, bool sse, hipStream_t s) {
   const size_t sh = size_t(fp.F) * fp.R * sizeof(float) + size_t(fp.R) * sizeof(double) +
                     size_t(fp.G) * 4 * sizeof(double) + 16;
   const int nb = c.n_spans * c.n_groups;
   if (sse)
-    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, true>), dim3(nb), dim3(W * 64), sh, s, fp);
+    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, true, NP>), dim3(nb), dim3(W * 64), sh, s, fp);
   else
-    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, false>), dim3(nb), dim3(W * 64), sh, s, fp);
+    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, false, NP>), dim3(nb), dim3(W * 64), sh, s, fp);
   return hipGetLastError();
+}
+
+template <typename T, int K, int D, int W>
+static hipError_t fused_np(const TileCfg& c, const FwdParams& fp, bool sse, hipStream_t s) {
+  switch (c.NP) {
+    case 1: return fused_impl<T, K, D, W, 1>(c, fp, sse, s);
+    case 2: return fused_impl<T, K, D, W, 2>(c, fp, sse, s);
+    case 4: return fused_impl<T, K, D, W, 4>(c, fp, sse, s);
+    case 8: return fused_impl<T, K, D, W, 8>(c, fp, sse, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fused_forward(bool fp64, const TileCfg& c, const uint2* uops, int U_stride,
@@ -177,13 +197,14 @@ hipError_t launch_fused_forward(bool fp64, const TileCfg& c, const uint2* uops, 
                                 const double* stats, double* part, bool want_sse, hipStream_t s) {
   FwdParams fp{uops, U_stride, meta, M, d.X, d.ldx, d.F, d.N, d.y, stats, part,
                c.R, c.G, c.n_groups, c.n_spans, c.tiles_per_span};
-  if (fp64) return fused_impl<double, 4, 8, 4>(c, fp, want_sse, s);
+  if (fp64) return fused_np<double, 4, 8, 4>(c, fp, want_sse, s);
+  if (c.D <= 4 && c.NP != 1) return hipErrorInvalidValue;
   if (c.K == 4) {
-    if (c.D <= 4) return fused_impl<float, 4, 4, 4>(c, fp, want_sse, s);
-    return fused_impl<float, 4, 8, 4>(c, fp, want_sse, s);
+    if (c.D <= 4) return fused_impl<float, 4, 4, 4, 1>(c, fp, want_sse, s);
+    return fused_np<float, 4, 8, 4>(c, fp, want_sse, s);
   }
-  if (c.D <= 4) return fused_impl<float, 8, 4, 4>(c, fp, want_sse, s);
-  return fused_impl<float, 8, 8, 4>(c, fp, want_sse, s);
+  if (c.D <= 4) return fused_impl<float, 8, 4, 4, 1>(c, fp, want_sse, s);
+  return fused_np<float, 8, 8, 4>(c, fp, want_sse, s);
 }
 
 // ------------------------------------------------------------------ finalize
@@ -239,6 +260,8 @@ __device__ inline void finalize_one(double A, double B, double C, double E, doub
   }
 }
 
+// One wave per individual: lane l sums spans l, l+64, ... in order, then a
+// fixed xor-tree over the wave (bitwise repeatable for a given span count).
 __global__ __launch_bounds__(256) void k_finalize(const ProgMeta* __restrict__ meta, int M,
                                                   const double* __restrict__ part, int n_spans,
                                                   const double* __restrict__ stats, uint32_t flags,
@@ -246,28 +269,34 @@ __global__ __launch_bounds__(256) void k_finalize(const ProgMeta* __restrict__ m
                                                   double* __restrict__ aux,
                                                   int8_t* __restrict__ status,
                                                   double* __restrict__ ab) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  double A = 0, B = 0, C = 0, E = 0;
+  const int i = __builtin_amdgcn_readfirstlane(int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+  if (i >= M) return;  // whole wave
+  const int lane = threadIdx.x & 63;
   const ProgMeta pm = meta[i];
+  double A = 0, B = 0, C = 0, E = 0;
   if (pm.status == 0) {
     const double* q = part + size_t(i) * n_spans * 4;
-    for (int s = 0; s < n_spans; ++s) {
+    for (int s = lane; s < n_spans; s += 64) {
       A += q[4 * s + 0];
       B += q[4 * s + 1];
       C += q[4 * s + 2];
       E += q[4 * s + 3];
     }
   }
-  finalize_one(A, B, C, E, double(pm.mu), stats, flags, pm.status, fitness + i,
-               aux ? aux + size_t(i) * 4 : nullptr, status ? status + i : nullptr,
-               ab ? ab + size_t(i) * 2 : nullptr);
+  A = wave_sum(A);
+  B = wave_sum(B);
+  C = wave_sum(C);
+  E = wave_sum(E);
+  if (lane == 0)
+    finalize_one(A, B, C, E, double(pm.mu), stats, flags, pm.status, fitness + i,
+                 aux ? aux + size_t(i) * 4 : nullptr, status ? status + i : nullptr,
+                 ab ? ab + size_t(i) * 2 : nullptr);
 }
 
 hipError_t launch_finalize(const ProgMeta* meta, int M, const double* part, int n_spans,
                            const double* stats, uint32_t flags, double* fitness, double* aux,
                            int8_t* status, double* ab, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3((M + 255) / 256), dim3(256), 0, s, meta, M, part, n_spans,
+  hipLaunchKernelGGL(k_finalize, dim3((M + 3) / 4), dim3(256), 0, s, meta, M, part, n_spans,
                      stats, flags, fitness, aux, status, ab);
   return hipGetLastError();
 }
@@ -317,7 +346,7 @@ __global__ __launch_bounds__(W * 64) void k_plain_fwd(PlainParams p) {
       const int nbatch = (nvalid + BR - 1) / BR;
       for (int b = w; b < nbatch; b += W) {
         const int lrow = b * BR + lane * K;
-        const auto v = run_program<T, K, D>(p.prog, xs, R, lrow);
+        const auto v = run_program<T, K, D>(UopMem{p.prog}, xs, R, lrow);
         accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
       }
     }

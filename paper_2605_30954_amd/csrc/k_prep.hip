@@ -28,55 +28,54 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_ysum(const float* __restrict__ y, int64_t N,
-                                              double* __restrict__ part) {
-  __shared__ double sh[256];
+__global__ __launch_bounds__(kStatBlocks) void k_ysum(const float* __restrict__ y, int64_t N,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[kStatBlocks];
   double acc = 0.0;
-  for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < N; r += int64_t(gridDim.x) * 256)
+  for (int64_t r = int64_t(blockIdx.x) * kStatBlocks + threadIdx.x; r < N;
+       r += int64_t(gridDim.x) * kStatBlocks)
     acc += double(y[r]);
-  const double s = block_sum<256>(acc, sh);
+  const double s = block_sum<kStatBlocks>(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__device__ inline double mean_from(const double* part, int n, int64_t N) {
-  double s = 0.0;
-  for (int b = 0; b < n; ++b) s += part[b];
-  return s / double(N);
+// Sum of the kStatBlocks partials, one per thread, in a fixed tree order.
+__device__ inline double sum_partials(const double* __restrict__ part, double* sh) {
+  return block_sum<kStatBlocks>(part[threadIdx.x], sh);
 }
 
-__global__ __launch_bounds__(256) void k_ydev(const float* __restrict__ y, int64_t N,
-                                              const double* __restrict__ psum,
-                                              double* __restrict__ pdev, double* __restrict__ pss) {
-  __shared__ double sh[256];
-  __shared__ double ybar_s;
-  if (threadIdx.x == 0) ybar_s = mean_from(psum, gridDim.x, N);
-  __syncthreads();
-  const double ybar = ybar_s;
+__global__ __launch_bounds__(kStatBlocks) void k_ydev(const float* __restrict__ y, int64_t N,
+                                                      const double* __restrict__ psum,
+                                                      double* __restrict__ pdev,
+                                                      double* __restrict__ pss) {
+  __shared__ double sh[kStatBlocks];
+  const double ybar = sum_partials(psum, sh) / double(N);
   double a = 0.0, b = 0.0;
-  for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < N; r += int64_t(gridDim.x) * 256) {
+  for (int64_t r = int64_t(blockIdx.x) * kStatBlocks + threadIdx.x; r < N;
+       r += int64_t(gridDim.x) * kStatBlocks) {
     const double d = double(y[r]) - ybar;
     a += d;
     b = fma(d, d, b);
   }
-  const double sa = block_sum<256>(a, sh);
-  const double sb = block_sum<256>(b, sh);
+  const double sa = block_sum<kStatBlocks>(a, sh);
+  const double sb = block_sum<kStatBlocks>(b, sh);
   if (threadIdx.x == 0) {
     pdev[blockIdx.x] = sa;
     pss[blockIdx.x] = sb;
   }
 }
 
-__global__ __launch_bounds__(64) void k_yfinal(const double* __restrict__ scratch, int nb, int64_t N,
-                                               double* __restrict__ stats) {
+// ybar, Var(y) = mean of (y - ybar)^2 minus the square of the mean deviation
+// (a rounding-level correction), and sum (y - ybar).
+__global__ __launch_bounds__(kStatBlocks) void k_yfinal(const double* __restrict__ scratch, int64_t N,
+                                                        double* __restrict__ stats) {
+  __shared__ double sh[kStatBlocks];
+  const double ybar = sum_partials(scratch, sh) / double(N);
+  const double sd = sum_partials(scratch + kStatBlocks, sh);
+  const double ss = sum_partials(scratch + 2 * kStatBlocks, sh);
   if (threadIdx.x != 0) return;
-  const double ybar = mean_from(scratch, nb, N);
-  double sd = 0.0, ss = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    sd += scratch[nb + b];
-    ss += scratch[2 * nb + b];
-  }
   const double md = sd / double(N);
-  double vy = ss / double(N) - md * md;
+  const double vy = ss / double(N) - md * md;
   stats[ST_YBAR] = ybar;
   stats[ST_VY] = vy > 0.0 ? vy : 0.0;
   stats[ST_YT] = sd;
@@ -84,11 +83,11 @@ __global__ __launch_bounds__(64) void k_yfinal(const double* __restrict__ scratc
 }
 
 hipError_t launch_ystats(const float* y, int64_t N, double* stats, double* scratch, hipStream_t s) {
-  const int nb = kStatBlocks;
-  hipLaunchKernelGGL(k_ysum, dim3(nb), dim3(256), 0, s, y, N, scratch);
-  hipLaunchKernelGGL(k_ydev, dim3(nb), dim3(256), 0, s, y, N, scratch, scratch + nb,
+  const int nb = kStatBlocks;  // blocks of the passes = threads of the partial sums
+  hipLaunchKernelGGL(k_ysum, dim3(nb), dim3(kStatBlocks), 0, s, y, N, scratch);
+  hipLaunchKernelGGL(k_ydev, dim3(nb), dim3(kStatBlocks), 0, s, y, N, scratch, scratch + nb,
                      scratch + 2 * nb);
-  hipLaunchKernelGGL(k_yfinal, dim3(1), dim3(64), 0, s, scratch, nb, N, stats);
+  hipLaunchKernelGGL(k_yfinal, dim3(1), dim3(kStatBlocks), 0, s, scratch, N, stats);
   return hipGetLastError();
 }
 
@@ -413,7 +412,7 @@ __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, i
   if (i >= M) return;
   if (meta[i].status != 0) return;
   const uint2* prog = uops + size_t(i) * U_stride;
-  const auto p = run_program<T, K, D>(prog, xs, R, lane * K);
+  const auto p = run_program<T, K, D>(UopMem{prog}, xs, R, lane * K);
   float s = 0.0f;
 #pragma unroll
   for (int j = 0; j < K; ++j) {

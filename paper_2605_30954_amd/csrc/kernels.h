@@ -27,6 +27,7 @@ struct TileCfg {
   int W = 4;               // waves per block
   int R = 1024;            // rows per LDS tile (multiple of 64*K)
   int G = 16;              // individuals per group (fused forward)
+  int NP = 1;              // VGPR pairs holding a program (uop_pairs(L_max))
   int tiles_per_span = 1;  // LDS tiles a block sweeps before writing partials
   int n_spans = 1;
   int n_groups = 1;
@@ -67,26 +68,36 @@ hipError_t launch_plain_forward(bool fp64, const TileCfg& c, int i, const uint2*
                                 double* ab, hipStream_t s);
 int plain_blocks(const TileCfg& c, int64_t N);
 
-// Adjoint launch plan: the register-tape kernel (reg) and the LDS-tape kernel
-// (wide) cut the rows into the same n_spans spans of span_rows rows.
+// Adjoint launch plan.  Individuals are split into tiers (register tape of
+// tc_a entries, register tape of tc_b entries, LDS tape); every tier cuts the
+// rows into the same n_spans spans of span_rows rows.  A tier's n_groups is
+// the number of group slots its grid holds per span.
 struct AdjPlan {
-  TileCfg reg, wide;
+  TileCfg reg, reg_b, wide;
   int n_spans = 1;
   int64_t span_rows = 0;
-  int reg_tape = 16;     // register tape entries of the reg kernel
-  int lane_consts = 16;  // per-lane constant columns of the reg kernel
-  int tape_cap = 1;      // LDS tape entries per wave of the wide kernel
-  bool need_wide = true; // some program of this shape may exceed the reg kernel
+  int tc_a = 16, tc_b = 32;  // register tape entries of tiers A and B
+  int lane_consts = 16;      // per-lane constant columns of the register tiers
+  int tape_cap = 1;          // LDS tape entries per wave of tier C
+  bool need_b = true;        // some program of this shape may fall in tier B
+  bool need_wide = true;     // ... in tier C
 };
 
-// adjoint: gradient partials gpart[i][span][C_max]; both kernels must run
-// (each writes the partials of the individuals it owns)
-hipError_t launch_adjoint_reg(const AdjPlan& a, const uint2* uops, int U_stride,
+// Tier lists: lists[tier * M + k], counts[tier], tier = 0, 1, 2 (after finalize).
+hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
+                                    int* lists, int* counts, hipStream_t s);
+// Plain form: counts[3i + tier] = 1 for individual i's tier, list0[0] = 0.
+hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
+                                     int* counts, int* list0, hipStream_t s);
+// gradient partials gpart[i][span][C_max] of the individuals list[0 .. *count)
+hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                              const double* stats, const double* ab, double* gpart, hipStream_t s);
+                              const double* stats, const double* ab, double* gpart,
+                              const int* list, const int* count, hipStream_t s);
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
-                              const double* stats, const double* ab, double* gpart, hipStream_t s);
+                              const double* stats, const double* ab, double* gpart,
+                              const int* list, const int* count, hipStream_t s);
 hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const double* gpart,
                                 int n_spans, const double* stats, const double* ab,
                                 uint32_t flags, const int8_t* status, double* grad,

@@ -9,7 +9,8 @@ import numpy as np
 
 from .configs import Config
 
-STREAM_X, STREAM_NOISE, STREAM_POP, STREAM_GOM = 0, 1, 2, 3
+STREAM_X, STREAM_NOISE, STREAM_POP, STREAM_GOM, STREAM_REDRAW = 0, 1, 2, 3, 4
+F32_MAX = float(np.finfo(np.float32).max)
 
 
 def rng_for(cid: int, stream: int, salt: int = 0) -> np.random.Generator:
@@ -33,7 +34,24 @@ def make_dataset(cfg: Config, N: int = None, salt: int = 0):
     xr = X32.astype(np.float64)
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         y64 = cfg.target(xr)
+    # a row whose target is not a finite float32 (e.g. a division by an exact
+    # zero of the rounded inputs) is redrawn from its own stream; other rows
+    # keep their values
+    redraw = rng_for(cfg.cid, STREAM_REDRAW, salt)
+    bad = ~(np.abs(y64) <= F32_MAX)
+    while np.any(bad):
+        cols = np.nonzero(bad)[0]
+        if cfg.x_dist == "N":
+            xn = redraw.standard_normal((cfg.F, cols.size))
+        else:
+            xn = redraw.uniform(cfg.x_lo, cfg.x_hi, (cfg.F, cols.size))
+        X32[:, cols] = xn.astype(np.float32)
+        xr[:, cols] = X32[:, cols].astype(np.float64)
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            y64[cols] = cfg.target(xr[:, cols])
+        bad = ~(np.abs(y64) <= F32_MAX)
     if cfg.noise:
         y64 = y64 + cfg.noise * rng_for(cfg.cid, STREAM_NOISE, salt).standard_normal(N)
     y32 = y64.astype(np.float32)
+    assert np.all(np.isfinite(y32))
     return X32, y32

@@ -44,10 +44,10 @@ def oracle_scores(d, idx, linear_scaling=True, precision="f32"):
                                   linear_scaling=linear_scaling, rng=precision, indices=idx)
 
 
-def oracle_flags(d, idx, precision="f32", linear_scaling=True, with_grad=False):
+def oracle_flags(d, idx, precision="f32", linear_scaling=True, with_grad=False, n=8):
     rtol = GATE[precision][0]
     return OM.flags(d["genes"], d["gc"], d["hs"], d["X"], d["y"], precision=precision, rtol=rtol,
-                    linear_scaling=linear_scaling, with_grad=with_grad, indices=idx)
+                    linear_scaling=linear_scaling, with_grad=with_grad, indices=idx, n=n)
 
 
 def gate_fitness(f_gpu, st_gpu, ref, flagged, vy, precision, what=""):
