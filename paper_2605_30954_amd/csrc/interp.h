@@ -201,6 +201,20 @@ struct VOps {
 #undef GG_MAP2
 };
 
+// Operand prefetch: the first variable operand of uop header h (its load
+// prefix if that is a variable, else its source if that is a variable) is read
+// from the row tile into `pre`, so that the LDS latency overlaps the work of
+// the uop before it.
+template <typename T, int K>
+__device__ inline void prefetch_operand(uint32_t h, const float* __restrict__ xl, int rstride,
+                                        typename VecT<T, K>::type& pre) {
+  if (uop_load(h) == LD_VAR) { pre = lds_rows<T, K>(xl + uop_load_arg(h) * rstride); GG_BRANCH(); }
+  if (uop_load(h) != LD_VAR && uop_src(h) == SRC_VAR) {
+    pre = lds_rows<T, K>(xl + uop_src_arg(h) * rstride);
+    GG_BRANCH();
+  }
+}
+
 // Evaluate the program on K rows per lane; returns the predictions.
 //   prog    uop source of this individual (UopMem or UopRegs)
 //   xt      LDS row tile: feature k, row r at xt[k*rstride + r]
@@ -212,9 +226,10 @@ __device__ inline typename VecT<T, K>::type run_program(const Src& prog,
   using V = typename VecT<T, K>::type;
   using O = VOps<T, K>;
   Slots<V, D> st;
-  V acc = T(0), t = T(0);
+  V acc = T(0), t = T(0), pre = T(0);
   const float* __restrict__ xl = xt + lrow;
   uint2 cur = prog.at(0);
+  prefetch_operand<T, K>(cur.x, xl, rstride, pre);
   int pc = 0;
 #pragma unroll 1
   for (;;) {
@@ -223,17 +238,24 @@ __device__ inline typename VecT<T, K>::type run_program(const Src& prog,
     const uint32_t op = uop_op(h);
     if (op == UOP_END) break;
     const uint32_t ld = uop_load(h);
+    const uint32_t sk = uop_src(h);
     const T c = T(f32_of(cur.y));
-    // load prefix: the first leaf of a subtree (after pushing the pending value)
+    // load prefix: the first leaf of a subtree (after pushing the pending value);
+    // the first variable operand was read one uop ahead into `pre`
     if (ld != LD_NONE) {
       if (h & HDR_PUSH) { st.put(uop_push_slot(h), acc); GG_BRANCH(); }
-      if (ld == LD_VAR) { acc = lds_rows<T, K>(xl + uop_load_arg(h) * rstride); GG_BRANCH(); }
+      if (ld == LD_VAR) { acc = pre; GG_BRANCH(); }
       if (ld == LD_CONST) { acc = c; GG_BRANCH(); }
       GG_BRANCH();
     }
-    const uint32_t sk = uop_src(h);
-    if (sk == SRC_VAR) { t = lds_rows<T, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
+    if (sk == SRC_VAR) {
+      if (ld == LD_VAR) { t = lds_rows<T, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
+      if (ld != LD_VAR) { t = pre; GG_BRANCH(); }
+      GG_BRANCH();
+    }
     if (sk == SRC_POP) { st.get(uop_src_arg(h), t); GG_BRANCH(); }
+    // `pre` is consumed: start reading the next uop's first variable operand
+    prefetch_operand<T, K>(nxt.x, xl, rstride, pre);
     if (op <= UOP_MUL) {
       if (sk == SRC_CONST) {  // the constant stays a scalar operand
         if (op == UOP_ADD) { acc = acc + c; GG_BRANCH(); }

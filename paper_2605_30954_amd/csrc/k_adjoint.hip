@@ -183,9 +183,10 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
   using P = Prot<float>;
   using Dv = Deriv<float>;
   Slots<V, D> st;
-  V acc = 0.0f, t = 0.0f, fa = 1.0f, fs = 1.0f;
+  V acc = 0.0f, t = 0.0f, fa = 1.0f, fs = 1.0f, pre = 0.0f;
   const float* __restrict__ xl = xt + lrow;
   uint2 cur = prog.at(0);
+  prefetch_operand<float, K>(cur.x, xl, rstride, pre);
   int pc = 0, tp = 0;
 #pragma unroll 1
   for (;;) {
@@ -194,16 +195,21 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
     const uint32_t op = uop_op(h);
     if (op == UOP_END) break;
     const uint32_t ld = uop_load(h);
+    const uint32_t sk = uop_src(h);
     const float c = f32_of(cur.y);
     if (ld != LD_NONE) {
       if (h & HDR_PUSH) { st.put(uop_push_slot(h), acc); GG_BRANCH(); }
-      if (ld == LD_VAR) { acc = lds_rows<float, K>(xl + uop_load_arg(h) * rstride); GG_BRANCH(); }
+      if (ld == LD_VAR) { acc = pre; GG_BRANCH(); }
       if (ld == LD_CONST) { acc = c; GG_BRANCH(); }
       GG_BRANCH();
     }
-    const uint32_t sk = uop_src(h);
-    if (sk == SRC_VAR) { t = lds_rows<float, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
+    if (sk == SRC_VAR) {
+      if (ld == LD_VAR) { t = lds_rows<float, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
+      if (ld != LD_VAR) { t = pre; GG_BRANCH(); }
+      GG_BRANCH();
+    }
     if (sk == SRC_POP) { st.get(uop_src_arg(h), t); GG_BRANCH(); }
+    prefetch_operand<float, K>(nxt.x, xl, rstride, pre);  // next uop's first variable
     if (sk == SRC_CONST) { t = c; GG_BRANCH(); }
     if (op == UOP_ADD) { acc = acc + t; GG_BRANCH(); }
     if (op == UOP_SUB) { acc = acc - t; GG_BRANCH(); }
@@ -272,7 +278,9 @@ struct LaneSink {
     float s = 0.0f;
 #pragma unroll
     for (int j = 0; j < K; ++j) s += j < kv ? v[j] : 0.0f;
-    col[c * kColStride] += s;
+    // read-modify-write inside the LDS unit (ds_add_f32, no return value, so
+    // nothing waits on it); only this lane writes this word, in program order
+    (void)atomicAdd(&col[c * kColStride], s);
   }
 };
 
