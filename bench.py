@@ -30,6 +30,74 @@ SYM_NAME = {0: "add", 1: "sub", 2: "mul", 3: "div", 4: "sin", 5: "cos", 6: "sq",
             8: "exp", 9: "log", 10: "pow"}
 
 
+# sources the adjoint kernels are built from: a traffic summary is valid only
+# for the kernels it was measured on
+ADJ_SOURCES = ["paper_2605_30954_amd/csrc/k_adjoint.hip", "paper_2605_30954_amd/csrc/interp.h",
+               "paper_2605_30954_amd/csrc/devmath.h", "paper_2605_30954_amd/csrc/uop.h",
+               "paper_2605_30954_amd/csrc/kernels.h"]
+ADJ_KERNELS = ("k_adj_partition", "k_adj_reg", "k_adj_lds")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_cfg2_traffic.json")
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ADJ_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pmc_summary(fetch_csv, write_csv, copy_bytes, out_json):
+    """HBM traffic per launch of the adjoint pair from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+    counter reads for the device-to-device copy of copy_bytes that the profiled
+    bench run ends with (--copy-probe-mb)."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+
+    out = {"kernel_src_sha256": sources_sha(), "copy_probe_bytes": copy_bytes}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        vals = per_kernel(path, counter)
+        copies = [v for k, vs in vals.items() if "copyBuffer" in k for v in vs]
+        big = [v for v in copies if v > 0.25 * copy_bytes]
+        probe = statistics.median(big)
+        scale = copy_bytes / probe
+        # the adjoint pair runs once per gradient step: sum the median dispatch
+        # of each of its kernels
+        adj = 0.0
+        for k, vs in vals.items():
+            if any(name in k for name in ADJ_KERNELS):
+                adj += statistics.median(vs)
+        out[counter] = {"scale": scale, "probe_counter_bytes": probe,
+                        "adjoint_counter_bytes": adj, "adjoint_bytes": adj * scale}
+    out["adjoint_traffic_bytes"] = out["FETCH_SIZE"]["adjoint_bytes"] + out["WRITE_SIZE"]["adjoint_bytes"]
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def load_traffic():
+    """Measured HBM bytes per adjoint launch, or None if the summary is missing
+    or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha256") != sources_sha():
+        return None
+    return t.get("adjoint_traffic_bytes")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,23 +113,11 @@ def parse():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device 3 times "
                          "(a plain copy of known size, to scale HBM traffic counters)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MB"),
+                    help="write the adjoint traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--tune-cache", default=None,
                     help="tuning file: loaded if it exists, else written by the autotuner")
     return ap.parse_args()
-
-
-def op_counts(ops_np):
-    """Per-operator token counts and terminal count over the whole batch."""
-    import numpy as np
-    counts = {}
-    vals, cnt = np.unique(ops_np[ops_np >= 0], return_counts=True)
-    term = 0
-    for v, c in zip(vals.tolist(), cnt.tolist()):
-        if v in SYM_NAME:
-            counts[SYM_NAME[v]] = counts.get(SYM_NAME[v], 0) + int(c)
-        else:
-            term += int(c)
-    return counts, term
 
 
 # derivative work per node in the adjoint's forward sweep, in operator costs
@@ -73,23 +129,55 @@ ARITY = {"add": 2, "sub": 2, "mul": 2, "div": 2, "pow": 2, "sin": 1, "cos": 1, "
          "sqrt": 1, "exp": 1, "log": 1}
 
 
-def roofline(gg, ops, cfg, N, stream, step, steps):
-    """Algorithmic lane-operations of the dominant kernel per launch over its
+def program_work(ops, status, s1, nconst, c):
+    """Algorithmic lane-operations per row, summed over the batch, from the
+    encoded programs.  Forward: every operator of every program with status 0
+    costs c(op), plus one moment update per program.  Adjoint (programs with
+    status 0, b != 0 and at least one constant, the only ones it evaluates):
+    every operator costs c(op); an operator with a constant below it adds its
+    local partials c(d op), and each of its children with a constant below
+    adds one product on the reverse sweep (none for + and -, whose partials
+    are +-1)."""
+    fwd = adj = 0.0
+    for m in range(ops.shape[0]):
+        if status[m] != 0:
+            continue
+        live = s1[m] != 0.0 and nconst[m] > 0
+        stack = []
+        f = a = 0.0
+        for tok in ops[m].tolist():
+            if tok < 0:
+                break
+            if tok not in SYM_NAME:        # constant (32) or variable (64 + k)
+                stack.append(tok == 32)
+                continue
+            name = SYM_NAME[tok]
+            kids = [stack.pop() for _ in range(ARITY[name])]
+            f += c[name]
+            a += c[name]
+            if any(kids):
+                a += sum(c[o] * w for o, w in DERIV[name].items())
+                if name not in ("add", "sub"):
+                    a += sum(kids) * c["mul"]
+            stack.append(any(kids))
+        fwd += f + c["moments"]
+        if live:
+            adj += a
+    return fwd, adj
+
+
+def roofline(gg, ops, cfg, N, stream, step, steps, fit_aux):
+    """Algorithmic lane-ops of the dominant kernel per launch over its
     measured average launch time.  An operator's cost c(op) is the lane-op
     slots one application takes at the chip's peak, measured by the library's
-    operator benchmark (c = seconds per lane-application x peak).  Forward:
-    sum over nodes of c(op) x N, plus the moment update per (individual, row).
-    Adjoint: the forward sweep with every node's local partials plus one
-    product per partial on the reverse sweep."""
+    operator benchmark (c = seconds per lane-application x peak); the work of
+    each kernel is program_work's count times N rows."""
     import torch
     costs = gg.op_costs()
     c = {k: v * PEAK_LANE_OPS for k, v in costs.items()}
-    counts, nterm = op_counts(ops)
-    fwd = sum(c[k] * n for k, n in counts.items())
-    deriv = sum(n * sum(c[o] * w for o, w in DERIV[k].items()) for k, n in counts.items())
-    rev = sum(n * ARITY[k] * c["mul"] for k, n in counts.items())
-    alg = {"fused_forward": (fwd + c["moments"] * cfg.M) * N,
-           "adjoint": (fwd + deriv + rev) * N}
+    st, s1, nconst = fit_aux
+    fwd_row, adj_row = program_work(ops, st, s1, nconst, c)
+    alg = {"fused_forward": fwd_row * N, "adjoint": adj_row * N}
     gg.profile(True)
     with torch.cuda.stream(stream):
         for _ in range(steps):
@@ -108,10 +196,14 @@ def roofline(gg, ops, cfg, N, stream, step, steps):
     avg_s = cand[dom] * 1e-3 / max(1.0, launches.get("fused_forward" if dom == "fused_forward"
                                                      else "adjoint_reg", 1.0))
     achieved = alg[dom] / avg_s
+    fwd_s = per.get("fused_forward", 0.0) * 1e-3
+    traffic = load_traffic() if dom == "adjoint" else None
     return {"bound": "alu", "kernel": dom if dom != "adjoint" else "+".join(k for k in adj_parts if k in per),
             "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "T lane-op/s",
-            "frac": achieved / PEAK_LANE_OPS, "traffic": None, "avg_launch_ms": avg_s * 1e3,
+            "frac": achieved / PEAK_LANE_OPS, "traffic": traffic, "traffic_unit": "bytes per launch",
+            "avg_launch_ms": avg_s * 1e3,
             "alg_lane_ops_per_launch": alg[dom],
+            "forward_frac": (alg["fused_forward"] / fwd_s / PEAK_LANE_OPS) if fwd_s else None,
             "kernels_ms_per_step": per,
             "op_cost_lane_ops": {k: round(v, 2) for k, v in c.items()}}
 
@@ -161,6 +253,10 @@ def cpu_baseline(cfg, d, fit_gpu, grad_gpu, st_gpu, seconds):
 
 def main():
     a = parse()
+    if a.pmc_summary:
+        f, w, mb = a.pmc_summary
+        print(json.dumps(pmc_summary(f, w, int(mb) << 20, TRAFFIC_FILE)))
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU sharding "
               "of this path is a design, not built", file=sys.stderr)
@@ -254,7 +350,9 @@ def main():
 
     # ---- roofline of the dominant kernel (per-kernel hipEvents on the stream)
     if not a.no_roofline:
-        out["roofline"] = roofline(gg, ops, cfg, N, stream, step, a.steps)
+        _, _, aux_r, st_r = gg.grad_consts(ops_d, cs_d, X_d, y_d, return_aux=True, return_status=True)
+        fit_aux = (st_r.cpu().numpy(), aux_r[:, 1].cpu().numpy(), nconst)
+        out["roofline"] = roofline(gg, ops, cfg, N, stream, step, a.steps, fit_aux)
 
     if not a.no_cpu_baseline:
         d = {"X": X, "y": y, "genes": genes, "gc": gc, "hs": hs, "lens": lens}

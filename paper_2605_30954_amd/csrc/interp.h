@@ -156,6 +156,32 @@ struct UopRegs {
   }
 };
 
+// Sum of a binary64 value over the 64 lanes of a wave, returned to every lane
+// (wave-uniform).  Data-parallel-primitive moves only, no LDS traffic: an
+// inclusive scan inside each row of 16 lanes (row_shr 1, 2, 4, 8), then the
+// row totals are carried across rows (row_bcast 15 into rows 1 and 3,
+// row_bcast 31 into rows 2 and 3), so lane 63 holds the total.  A lane with no
+// source reads 0.  Fixed pattern: bitwise repeatable.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROWS, 0xf, true);
+  return __longlong_as_double((long long)uint32_t(lo) | ((long long)hi << 32));
+}
+__device__ inline double wave_sum(double v) {
+  v += dpp_move<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b), 63);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+  return __longlong_as_double((long long)uint32_t(lo) | ((long long)hi << 32));
+}
+
 // Dynamic work queue of one block and one row tile: every wave claims the
 // next index from an LDS counter (one atomic by lane 0; the value is made
 // wave-uniform with readfirstlane, so loops on it exit with a scalar branch),

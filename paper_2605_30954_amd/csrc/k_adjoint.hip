@@ -182,6 +182,7 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
   using V = typename VecT<float, K>::type;
   using P = Prot<float>;
   using Dv = Deriv<float>;
+  using O = VOps<float, K>;
   Slots<V, D> st;
   V acc = 0.0f, t = 0.0f, fa = 1.0f, fs = 1.0f, pre = 0.0f;
   const float* __restrict__ xl = xt + lrow;
@@ -215,24 +216,97 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
     if (op == UOP_SUB) { acc = acc - t; GG_BRANCH(); }
     if (op == UOP_RSUB) { acc = t - acc; GG_BRANCH(); }
     if (op == UOP_MUL) { fa = t; fs = acc; acc = acc * t; GG_BRANCH(); }
-    if (op >= UOP_DIV) {
+    if (op >= UOP_DIV && !(h & (HDR_ADJ_ACC | HDR_ADJ_SRC))) {  // no constant below: value only
+      if (op == UOP_DIV) { acc = O::div(acc, t); GG_BRANCH(); }
+      if (op == UOP_RDIV) { acc = O::div(t, acc); GG_BRANCH(); }
+      if (op == UOP_POW) { acc = O::pow(acc, t); GG_BRANCH(); }
+      if (op == UOP_RPOW) { acc = O::pow(t, acc); GG_BRANCH(); }
+      if (op == UOP_SIN) { acc = O::sin(acc); GG_BRANCH(); }
+      if (op == UOP_COS) { acc = O::cos(acc); GG_BRANCH(); }
+      if (op == UOP_SQ) { acc = acc * acc; GG_BRANCH(); }
+      if (op == UOP_SQRT) { acc = O::sqrt(acc); GG_BRANCH(); }
+      if (op == UOP_EXP) { acc = O::exp(acc); GG_BRANCH(); }
+      if (op == UOP_LOG) { acc = O::log(acc); GG_BRANCH(); }
+      GG_BRANCH();
+    }
+    if (op >= UOP_DIV && (h & (HDR_ADJ_ACC | HDR_ADJ_SRC))) {  // value and local partials
+      if (op == UOP_DIV) {
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const float a = acc[j], b = t[j];
-        float v = a, da = 1.0f, ds = 1.0f;
-        if (op == UOP_DIV) { v = P::div(a, b); Dv::ddiv(a, b, v, da, ds); }
-        if (op == UOP_RDIV) { v = P::div(b, a); Dv::ddiv(b, a, v, ds, da); }
-        if (op == UOP_POW) { v = P::pow_(a, b); Dv::dpow(a, b, v, da, ds); }
-        if (op == UOP_RPOW) { v = P::pow_(b, a); Dv::dpow(b, a, v, ds, da); }
-        if (op == UOP_SIN) { v = P::sin_(a); da = Dv::dsin(a); }
-        if (op == UOP_COS) { v = P::cos_(a); da = Dv::dcos(a); }
-        if (op == UOP_SQ) { v = a * a; da = 2.0f * a; }
-        if (op == UOP_SQRT) { v = P::sqrt_(a); da = Dv::dsqrt(a, v); }
-        if (op == UOP_EXP) { v = P::exp_(a); da = Dv::dexp(a, v); }
-        if (op == UOP_LOG) { v = P::log_(a); da = Dv::dlog(a); }
-        acc[j] = v;
-        fa[j] = da;
-        fs[j] = ds;
+        for (int j = 0; j < K; ++j) {
+          const float v = P::div(acc[j], t[j]);
+          float da, ds;
+          Dv::ddiv(acc[j], t[j], v, da, ds);
+          acc[j] = v; fa[j] = da; fs[j] = ds;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_RDIV) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::div(t[j], acc[j]);
+          float da, ds;
+          Dv::ddiv(t[j], acc[j], v, ds, da);
+          acc[j] = v; fa[j] = da; fs[j] = ds;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_POW) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::pow_(acc[j], t[j]);
+          float da, ds;
+          Dv::dpow(acc[j], t[j], v, da, ds);
+          acc[j] = v; fa[j] = da; fs[j] = ds;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_RPOW) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::pow_(t[j], acc[j]);
+          float da, ds;
+          Dv::dpow(t[j], acc[j], v, ds, da);
+          acc[j] = v; fa[j] = da; fs[j] = ds;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_SIN) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = Dv::dsin(acc[j]); acc[j] = P::sin_(acc[j]); }
+        GG_BRANCH();
+      }
+      if (op == UOP_COS) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = Dv::dcos(acc[j]); acc[j] = P::cos_(acc[j]); }
+        GG_BRANCH();
+      }
+      if (op == UOP_SQ) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = 2.0f * acc[j]; acc[j] = acc[j] * acc[j]; }
+        GG_BRANCH();
+      }
+      if (op == UOP_SQRT) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::sqrt_(acc[j]);
+          fa[j] = Dv::dsqrt(acc[j], v);
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_EXP) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::exp_(acc[j]);
+          fa[j] = Dv::dexp(acc[j], v);
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_LOG) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = Dv::dlog(acc[j]); acc[j] = P::log_(acc[j]); }
+        GG_BRANCH();
       }
       GG_BRANCH();
     }
@@ -252,9 +326,7 @@ __device__ inline double wave_total(const typename VecT<float, K>::type& v, int 
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < K; ++j) s += j < kv ? double(v[j]) : 0.0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  return s;
+  return wave_sum(s);
 }
 
 // Where constant adjoints go.  WaveSink: reduced across the wave at once and
@@ -651,8 +723,7 @@ __global__ __launch_bounds__(256) void k_grad_finalize(const ProgMeta* __restric
     const double* q = gpart + size_t(i) * n_spans * C_max + j;
     for (int s = lane; s < n_spans; s += 64) g += q[size_t(s) * C_max];
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+  g = wave_sum(g);
   if (lane == 0) grad[idx] = live ? g * (2.0 * s1 / stats[ST_N]) : 0.0;
 }
 

@@ -55,12 +55,6 @@ struct Moments {
   }
 };
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
 // Accumulate K predictions of this lane into the moments.
 template <typename T, int K, bool SSE>
 __device__ inline void accumulate(Moments<SSE>& m, const typename VecT<T, K>::type& p,
