@@ -202,7 +202,7 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   const int BRr = 64 * r.K;
   const size_t tile_cap = t ? size_t(cap) : size_t(32 * 1024);
   while (r.R > BRr && (size_t(s.F) * r.R * 4 + size_t(r.R) * 8 > tile_cap ||
-                       adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts) > size_t(cap)))
+                       adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts, 1) > size_t(cap)))
     r.R /= 2;
   const int64_t Nr = (s.N + 255) / 256 * 256;  // a multiple of every tier's batch
   if (Nr < r.R) r.R = int(Nr);
@@ -222,9 +222,14 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   // and at most C_max constants, so small shapes never reach tier B or C.
   a.tape_cap = std::max(1, s.L_max - 1);
   a.need_b = a.tape_cap > a.tc_a && a.tc_b > a.tc_a;
+  // tier B: few individuals, each shared by the block's waves; G_b of them
+  // per group, a bounded number of group slots per span (blocks loop)
   TileCfg& b = a.reg_b;
   b = r;
   b.K = 2;
+  b.G = std::max(1, std::min(4, s.M));
+  while (b.G > 1 && adjoint_reg_lds_bytes(s.F, b.R, b.G, Cm, b.W, a.lane_consts, b.W) > size_t(cap)) --b.G;
+  b.n_groups = std::min((s.M + b.G - 1) / b.G, 32);
   a.need_wide = a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts;
 
   // tier C: its tile must divide span_rows (powers of two <= r.R)
@@ -267,8 +272,12 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
 }
 
 bool adjoint_plan_fits(const Shape& s, const AdjPlan& a) {
-  if (!a.need_wide) return true;
   const int cap = lds_limit_bytes() - 64;
+  const int Cm = std::max(1, s.C_max);
+  if (a.need_b &&
+      adjoint_reg_lds_bytes(s.F, a.reg_b.R, a.reg_b.G, Cm, a.reg_b.W, a.lane_consts, a.reg_b.W) > size_t(cap))
+    return false;
+  if (!a.need_wide) return true;
   return adjoint_lds_bytes(s.F, a.wide.R, a.wide.G, std::max(1, s.C_max), a.wide.W, a.wide.K,
                            a.tape_cap) <= size_t(cap) &&
          a.span_rows % a.wide.R == 0;

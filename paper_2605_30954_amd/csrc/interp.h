@@ -182,6 +182,26 @@ __device__ inline double wave_sum(double v) {
   return __longlong_as_double((long long)uint32_t(lo) | ((long long)hi << 32));
 }
 
+// Row-tile staging with direct global-to-LDS loads (global_load_lds_dword):
+// the W waves of the block issue the tile's 64-row chunks of every feature
+// back to back, with no register round trip and no wait per load; the caller
+// waits once (s_waitcnt 0) and barriers before reading.  Rows past the last
+// valid one read a clamped valid row: padding rows are masked by every
+// consumer.  R is a multiple of 64.
+template <int W>
+__device__ inline void stage_x_async(float* xs, const float* __restrict__ X, int64_t ldx, int F,
+                                     int R, int64_t r0, int64_t N) {
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int per = R >> 6;  // chunks per feature
+  const int nq = F * per;
+  for (int q = wv; q < nq; q += W) {  // wave-uniform
+    const int f = q / per, r = (q - f * per) << 6;
+    const int64_t row = min<int64_t>(r0 + r + lane, N - 1);
+    __builtin_amdgcn_global_load_lds(X + size_t(f) * ldx + row, xs + size_t(f) * R + r, 4, 0, 0);
+  }
+}
+
 // Dynamic work queue of one block and one row tile: every wave claims the
 // next index from an LDS counter (one atomic by lane 0; the value is made
 // wave-uniform with readfirstlane, so loops on it exit with a scalar branch),

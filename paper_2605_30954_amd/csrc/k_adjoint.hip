@@ -410,16 +410,17 @@ __device__ inline AdjItem adj_item(const AdjParams& p) {
   return {span, item - span * p.n_groups};
 }
 
-// Stage one row tile of X (feature-major, zero past the last row) and the
-// centred targets into LDS.
+// Stage one row tile of X (feature-major; rows past the last valid one hold
+// a copy of a valid row and are masked by adj_seed and the sinks) and the
+// centred targets (zero past the last row) into LDS.  The caller barriers.
+template <int W>
 __device__ inline void adj_stage(const AdjParams& p, float* xs, double* yts, int64_t r0, int nvalid,
                                  double ybar) {
-  for (int f = 0; f < p.F; ++f) {
-    const float* __restrict__ src = p.X + size_t(f) * p.ldx + r0;
-    for (int r = threadIdx.x; r < p.R; r += blockDim.x) xs[size_t(f) * p.R + r] = r < nvalid ? src[r] : 0.0f;
-  }
+  stage_x_async<W>(xs, p.X, p.ldx, p.F, p.R, r0, p.N);
+#pragma unroll 4
   for (int r = threadIdx.x; r < p.R; r += blockDim.x)
     yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
+  __builtin_amdgcn_s_waitcnt(0);  // the tile's direct loads have landed
 }
 
 // Per-row output adjoint: the residual (s0 - ybar) + s1 p - (y - ybar) in
@@ -447,15 +448,44 @@ __device__ inline void adj_write(const AdjParams& p, int span, int base, int Gn,
   }
 }
 
-template <int K, int D, int W, int TC, int NP>
+// Per-wave column sums of the constant adjoints (binary64), added to acc[c].
+template <int W>
+__device__ inline void reduce_columns(const float* lacc, int nc, int lane, double* acc) {
+  // the wave's column writes must land before lane c reads column c
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane < nc) {
+    const float* colc = lacc + lane * kColStride;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < 64; k += 4) {
+      a0 += double(colc[k]);
+      a1 += double(colc[k + 1]);
+      a2 += double(colc[k + 2]);
+      a3 += double(colc[k + 3]);
+    }
+    acc[lane] += (a0 + a1) + (a2 + a3);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// SPLIT = false (tier A): the waves claim whole individuals from the tile's
+// queue.  SPLIT = true (tier B, few individuals): all W waves share each
+// individual, wave w taking batches w, w+W, ... with its own copy of the
+// accumulators, summed in wave order at the end (bitwise repeatable).
+template <int K, int D, int W, int TC, int NP, bool SPLIT>
 __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int COPIES = SPLIT ? W : 1;
   const int R = p.R;
   const int CC = p.lane_consts;
   float* xs = reinterpret_cast<float*>(smem_raw);
   double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
-  double* gacc = yts + R;                                                     // G * C_max
-  float* lacc_all = reinterpret_cast<float*>(gacc + size_t(p.G) * p.C_max);  // W * CC * 65
+  double* gacc = yts + R;  // COPIES * G * C_max
+  float* lacc_all = reinterpret_cast<float*>(gacc + size_t(COPIES) * p.G * p.C_max);  // W * CC * 65
 
   const AdjItem it = adj_item(p);
   const int cnt = __builtin_amdgcn_readfirstlane(*p.count);
@@ -466,6 +496,8 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   constexpr int BR = 64 * K;
   float* lacc = lacc_all + size_t(wv) * CC * kColStride;
   LaneSink sink{lacc + lane};
+  const int GC = p.G * p.C_max;
+  double* gmine = gacc + (SPLIT ? size_t(wv) * GC : 0);
   const int64_t s_begin = int64_t(it.span) * p.span_rows;
   const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
 
@@ -474,29 +506,30 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
     const int base = grp * p.G;
     const int Gn = min(p.G, cnt - base);
     __syncthreads();  // previous group's partials written
-    for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) gacc[j] = 0.0;
+    for (int j = threadIdx.x; j < COPIES * GC; j += blockDim.x) gacc[j] = 0.0;
     for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
       const int nvalid = int(min<int64_t>(R, s_end - r0));
       __syncthreads();
       if (threadIdx.x == 0) queue = 0;
-      adj_stage(p, xs, yts, r0, nvalid, ybar);
+      adj_stage<W>(p, xs, yts, r0, nvalid, ybar);
       __syncthreads();
       const int nbatch = (nvalid + BR - 1) / BR;
-      // the waves claim the group's individuals from the tile's queue; the
-      // next one is claimed and its program loaded while this one runs
+      // the next individual (claimed from the queue, or simply the next one
+      // when the waves share each individual) has its program loaded into
+      // registers while this one runs
       UopRegs<NP> prog, prog_next;
-      int jj = claim_next(&queue);
+      int jj = SPLIT ? 0 : claim_next(&queue);
       if (jj < Gn) prog.load(p.uops + size_t(p.list[base + jj]) * p.U_stride, p.U_stride);
       while (jj < Gn) {  // wave-uniform
         const int i = __builtin_amdgcn_readfirstlane(p.list[base + jj]);
-        const int jn = claim_next(&queue);
+        const int jn = SPLIT ? jj + 1 : claim_next(&queue);
         if (jn < Gn) prog_next.load(p.uops + size_t(p.list[base + jn]) * p.U_stride, p.U_stride);
         const ProgMeta pm = p.meta[i];
         const int nc = __builtin_amdgcn_readfirstlane(pm.n_const);
         const double s1 = p.ab[size_t(i) * 2 + 1];
         const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
-        for (int b = 0; b < nbatch; ++b) {
+        for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
           const int lrow = b * BR + lane * K;
           RegTape<K, TC> tape;
           const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
@@ -504,31 +537,19 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
           const int kv = max(0, min(K, nvalid - lrow));
           run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
         }
-        // the wave's column writes must land before lane c reads column c
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < nc) {
-          const float* colc = lacc + lane * kColStride;
-          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 4
-          for (int k = 0; k < 64; k += 4) {
-            a0 += double(colc[k]);
-            a1 += double(colc[k + 1]);
-            a2 += double(colc[k + 2]);
-            a3 += double(colc[k + 3]);
-          }
-          gacc[size_t(jj) * p.C_max + lane] += (a0 + a1) + (a2 + a3);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        reduce_columns<W>(lacc, nc, lane, gmine + size_t(jj) * p.C_max);
         prog = prog_next;
         jj = jn;
       }
     }
     __syncthreads();
-    adj_write(p, it.span, base, Gn, gacc);
+    if constexpr (SPLIT) {
+      for (int j = threadIdx.x; j < GC; j += blockDim.x) {
+#pragma unroll
+        for (int w = 1; w < W; ++w) gacc[j] += gacc[size_t(w) * GC + j];
+      }
+    }
+    adj_write(p, it.span, base, Gn, gacc);  // each thread reads what it summed
   }
 }
 
@@ -567,7 +588,7 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
     for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
       const int nvalid = int(min<int64_t>(R, s_end - r0));
       __syncthreads();
-      adj_stage(p, xs, yts, r0, nvalid, ybar);
+      adj_stage<W>(p, xs, yts, r0, nvalid, ybar);
       __syncthreads();
       const int nbatch = (nvalid + BR - 1) / BR;
       for (int jj = 0; jj < Gn; ++jj) {  // uniform over the block
@@ -597,25 +618,29 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
 }
 
 template <int K, int D, int W, int TC, int NP>
-static hipError_t reg_impl1(const TileCfg& c, int CC, const AdjParams& ap, hipStream_t s) {
-  const size_t sh = adjoint_reg_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, CC);
-  hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP>), dim3(ap.n_spans * ap.n_groups), dim3(W * 64), sh, s,
-                     ap);
+static hipError_t reg_impl1(const TileCfg& c, int CC, bool split, const AdjParams& ap, hipStream_t s) {
+  const size_t sh = adjoint_reg_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, CC, split ? W : 1);
+  if (split)
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, true>), dim3(ap.n_spans * ap.n_groups), dim3(W * 64),
+                       sh, s, ap);
+  else
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false>), dim3(ap.n_spans * ap.n_groups),
+                       dim3(W * 64), sh, s, ap);
   return hipGetLastError();
 }
 
 // programs of up to 63 tokens use D = 4 (one register pair); longer ones D = 8
 template <int K, int D, int W, int TC>
-static hipError_t reg_impl(const TileCfg& c, int CC, const AdjParams& ap, hipStream_t s) {
+static hipError_t reg_impl(const TileCfg& c, int CC, bool split, const AdjParams& ap, hipStream_t s) {
   if constexpr (D == 4) {
     if (c.NP != 1) return hipErrorInvalidValue;
-    return reg_impl1<K, 4, W, TC, 1>(c, CC, ap, s);
+    return reg_impl1<K, 4, W, TC, 1>(c, CC, split, ap, s);
   } else {
     switch (c.NP) {
-      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, ap, s);
-      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, ap, s);
-      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, ap, s);
-      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, ap, s);
+      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, split, ap, s);
+      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, split, ap, s);
+      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, split, ap, s);
+      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, split, ap, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -676,13 +701,14 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
   const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
                                   gpart, list, count);
   const int CC = a.lane_consts;
+  const bool split = tier == 1;  // tier B: few individuals, the waves share each one
   if (c.W != 4) return hipErrorInvalidValue;
-  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, ap, s);
-  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, ap, s);
-  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, ap, s);
-  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, ap, s);
-  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, ap, s);
-  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, split, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 

@@ -119,9 +119,11 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     const int nvalid = int(min<int64_t>(R, p.N - r0));
     __syncthreads();  // previous tile fully consumed
     if (threadIdx.x == 0) queue = 0;
-    stage_tile(xs, p.X, p.ldx, p.F, R, r0, nvalid);
+    stage_x_async<W>(xs, p.X, p.ldx, p.F, R, r0, p.N);
+#pragma unroll 4
     for (int r = threadIdx.x; r < R; r += blockDim.x)
       yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
+    __builtin_amdgcn_s_waitcnt(0);  // the tile's direct loads have landed
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
     // the waves claim the group's individuals from the tile's queue (a

@@ -116,9 +116,11 @@ inline size_t adjoint_lds_bytes(int F, int R, int G, int C_max, int W, int K, in
   return off + size_t(W) * tape_cap * 64 * K * 4;
 }
 // LDS bytes of one register-tape adjoint block (row tile, centred targets,
-// constant accumulators, W waves x CC per-lane constant columns of 65 floats).
-inline size_t adjoint_reg_lds_bytes(int F, int R, int G, int C_max, int W, int CC) {
-  return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * C_max * 8 + size_t(W) * CC * 65 * 4;
+// `copies` sets of constant accumulators, W waves x CC per-lane constant
+// columns of 65 floats).
+inline size_t adjoint_reg_lds_bytes(int F, int R, int G, int C_max, int W, int CC, int copies) {
+  return size_t(F) * R * 4 + size_t(R) * 8 + size_t(copies) * G * C_max * 8 +
+         size_t(W) * CC * 65 * 4;
 }
 inline size_t forward_lds_bytes(int F, int R, int G) {
   return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * 4 * 8 + 16;
