@@ -34,7 +34,7 @@ SYM_NAME = {0: "add", 1: "sub", 2: "mul", 3: "div", 4: "sin", 5: "cos", 6: "sq",
 # for the kernels it was measured on
 ADJ_SOURCES = ["paper_2605_30954_amd/csrc/k_adjoint.hip", "paper_2605_30954_amd/csrc/interp.h",
                "paper_2605_30954_amd/csrc/devmath.h", "paper_2605_30954_amd/csrc/uop.h",
-               "paper_2605_30954_amd/csrc/kernels.h"]
+               "paper_2605_30954_amd/csrc/kernels.h", "paper_2605_30954_amd/build.py"]
 ADJ_KERNELS = ("k_adj_partition", "k_adj_reg", "k_adj_lds")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_cfg2_traffic.json")
 

@@ -36,7 +36,11 @@ def common_flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
             "-Wall", "-Wno-unused-function",
             # never emit packed FP32 math (v_pk_add/mul/fma_f32)
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # the interpreters branch on wave-uniform values only: leave uniform
+            # regions unstructurized (plain scalar branches, fewer flow blocks and
+            # fewer register copies at the joins)
+            "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 
 
 def compile_one(src, save_temps=False):
