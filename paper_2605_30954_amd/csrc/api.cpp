@@ -95,8 +95,8 @@ Layout layout_of(const Shape& s) {
   o = align256(o + 64);
   l.gpart = o;
   o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
-  l.adjl = o;  // adjoint tier lists [3][M] and counts [3][M] (per individual in the plain form)
-  o = align256(o + size_t(s.M) * 6 * sizeof(int32_t) + 64);
+  l.adjl = o;  // adjoint tier lists [4][M] + counts [4], or per-individual counts [M][4] + a list
+  o = align256(o + size_t(s.M) * 8 * sizeof(int32_t) + 64);
   l.tune = o;  // outputs of the autotuner's trial calls: fitness, grad, status
   o = align256(o + size_t(s.M) * (std::max(s.C_max, 1) + 2) * sizeof(double));
   l.total = o;
@@ -122,6 +122,7 @@ TuneKey tune_key(const Shape& s, bool grad) {
 struct Tuned {
   int K, R, G;
   int TC;  // adjoint tier A tape entries (0 for the forward)
+  int F;   // adjoint: 2 = forward mode for programs with <= 2 constants, 0 = reverse only
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuned> g_tuned;  // forward choices
@@ -231,6 +232,11 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   while (b.G > 1 && adjoint_reg_lds_bytes(s.F, b.R, b.G, Cm, b.W, a.lane_consts, b.W) > size_t(cap)) --b.G;
   b.n_groups = std::min((s.M + b.G - 1) / b.G, 32);
   a.need_wide = a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts;
+
+  // forward mode inside tier A: programs with at most nt_f constants
+  a.nt_f = 2;
+  if (t && t->F == 0) a.nt_f = 0;
+  a.need_f = a.nt_f > 0 && s.C_max > 0;
 
   // tier C: its tile must divide span_rows (powers of two <= r.R)
   TileCfg& w = a.wide;
@@ -375,13 +381,13 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
       const AdjPlan one = plan_adjoint(Shape{1, c.s.L_max, c.s.C_max, c.s.F, c.s.N, c.s.ldx, c.s.flags}, D,
                                        nullptr, adj_span_cap(c.s));
       int* pcounts = reinterpret_cast<int*>(c.ws + l.adjl);
-      int* list0 = pcounts + 3 * size_t(c.s.M);
+      int* list0 = pcounts + 4 * size_t(c.s.M);
       GG_TIMED("plain_tiers", launch_adjoint_tier_flags(one, meta, ab, c.s.M, pcounts, list0, c.stream));
       for (int i = 0; i < c.s.M; ++i) {
         const uint2* ui = uops + size_t(i) * l.U_stride;
         double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
         const double* abi = ab + 2 * size_t(i);
-        const int* ci = pcounts + 3 * size_t(i);
+        const int* ci = pcounts + 4 * size_t(i);
         GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
                                                      abi, gi, list0, ci + 0, c.stream));
         if (one.need_b)
@@ -402,7 +408,7 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
                                        c.status, ab, c.stream));
   if (c.with_grad) {
     int* lists = reinterpret_cast<int*>(c.ws + l.adjl);
-    int* counts = lists + 3 * size_t(c.s.M);
+    int* counts = lists + 4 * size_t(c.s.M);
     const size_t M = size_t(c.s.M);
     GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, c.stream));
     GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
@@ -443,7 +449,7 @@ int run_call(const Call& c) {
            uintptr_t(c.s.C_max), uintptr_t(c.s.F), uintptr_t(c.s.N), uintptr_t(c.s.ldx),
            uintptr_t(c.s.flags), uintptr_t(fc.K), uintptr_t(fc.R), uintptr_t(fc.G),
            uintptr_t(ac.reg.R), uintptr_t(ac.reg.G), uintptr_t(ac.reg.K), uintptr_t(ac.tc_a),
-           uintptr_t(ac.n_spans)};
+           uintptr_t(ac.n_spans), uintptr_t(ac.nt_f)};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -628,8 +634,9 @@ std::string tune_line(const char* table, const TuneKey& k, const Tuned& t) {
   char b[256];
   std::snprintf(b, sizeof(b),
                 "  {\"table\": \"%s\", \"fp64\": %d, \"Lcls\": %d, \"F\": %d, \"Ncls\": %d, "
-                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d, \"TC\": %d}",
-                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G, t.TC);
+                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d, \"TC\": %d, "
+                "\"TF\": %d}",
+                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G, t.TC, t.F);
   return b;
 }
 
@@ -662,6 +669,7 @@ bool read_tuning(const char* path, int* n_read) {
           json_int(line, "K", &t.K) && json_int(line, "R", &t.R) && json_int(line, "G", &t.G)))
       continue;
     if (!json_int(line, "TC", &t.TC)) t.TC = 0;
+    if (!json_int(line, "TF", &t.F)) t.F = 2;
     if (t.K < 1 || t.R < 64 || t.G < 1) continue;
     (fwd ? g_tuned : g_tuned_adj)[k] = t;
     ++n;
@@ -723,7 +731,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   const int Rs_f[5] = {256, 512, 1024, 2048, 4096};
   const int Gs_f[5] = {4, 8, 16, 32, 64};
   const int lds = lds_limit_bytes();
-  Tuned best_f{0, 0, 0, 0};
+  Tuned best_f{0, 0, 0, 0, 0};
   float best_f_ms = 1e30f;
   TileCfg fc_best;
   for (int k : Ks_f) {
@@ -732,7 +740,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
       if (r < 64 * k) continue;
       for (int g : Gs_f) {
         if (forward_lds_bytes(F, r, g) > size_t(lds)) continue;
-        const Tuned t{k, r, g, 0};
+        const Tuned t{k, r, g, 0, 0};
         const TileCfg fc = plan_forward(st, &t);
         const AdjPlan ac = plan_adjoint(st, fc.D, nullptr, adj_span_cap(s));
         const float ms = time_plans(c, fc, ac, trials);
@@ -760,13 +768,15 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     const int KT_a[3][2] = {{4, 16}, {2, 16}, {2, 32}};
     const int Rs_a[4] = {256, 512, 1024, 2048};
     const int Gs_a[4] = {4, 8, 16, 32};
-    Tuned best_a{0, 0, 0, 0};
+    const int Fs_a[2] = {2, 0};
+    Tuned best_a{0, 0, 0, 0, 0};
     float best_a_ms = 1e30f;
-    for (const auto& kt : KT_a) {
+    for (const auto& kt : KT_a)
+    for (int fv : Fs_a) {
       const int k = kt[0];
       for (int r : Rs_a) {
         for (int g : Gs_a) {
-          const Tuned t{k, r, g, kt[1]};
+          const Tuned t{k, r, g, kt[1], fv};
           const AdjPlan ac = plan_adjoint(st, fc_best.D, &t, adj_span_cap(s));
           if (ac.reg.R != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
           const float ms = time_plans(c, fc_best, ac, trials);
@@ -784,8 +794,8 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     if (best_a.K) {
       g_tuned_adj[tune_key(s, true)] = best_a;
       len += std::snprintf(desc + len, sizeof(desc) - size_t(len),
-                           "; fitness+gradient with adjoint K=%d TC=%d R=%d G=%d (%.3f ms)",
-                           best_a.K, best_a.TC, best_a.R, best_a.G, double(best_a_ms));
+                           "; fitness+gradient with adjoint K=%d TC=%d F=%d R=%d G=%d (%.3f ms)",
+                           best_a.K, best_a.TC, best_a.F, best_a.R, best_a.G, double(best_a_ms));
     }
   }
   if (cache_path) {

@@ -58,9 +58,13 @@ struct AdjParams {
 };
 
 // Tier of an individual: -1 no gradient work (bad program, non-finite, b = 0
-// or no constant), 0 register tape A, 1 register tape B, 2 LDS tape.
-__device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, int CC) {
+// or no constant), 0 tier A (register tape, or forward mode for at most ntF
+// constants: one tangent per constant, no tape), 1 register tape B, 2 LDS
+// tape.  (Slot 3 of the lists is unused.)
+constexpr int kTiers = 4;
+__device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, int CC, int ntF) {
   if (pm.status != 0 || s1 == 0.0 || pm.n_const <= 0) return -1;
+  if (pm.n_const <= ntF) return 0;  // forward mode inside the tier A kernel
   if (pm.n_const <= CC && pm.n_tape <= tcA) return 0;
   if (pm.n_const <= CC && pm.n_tape <= tcB) return 1;
   return 2;
@@ -72,46 +76,43 @@ __device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, 
 constexpr int kPartThreads = 1024;
 __global__ __launch_bounds__(kPartThreads) void k_adj_partition(
     const ProgMeta* __restrict__ meta, const double* __restrict__ ab, int M, int tcA, int tcB,
-    int CC, int* __restrict__ lists, int* __restrict__ counts) {
-  __shared__ int sc[3][kPartThreads];
+    int CC, int ntF, int* __restrict__ lists, int* __restrict__ counts) {
+  __shared__ int sc[kTiers][kPartThreads];
   const int t = threadIdx.x;
   const int chunk = (M + kPartThreads - 1) / kPartThreads;
   const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
-  int n0 = 0, n1 = 0, n2 = 0;
+  int n[kTiers] = {0, 0, 0, 0};
   for (int i = lo; i < hi; ++i) {
-    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC);
-    n0 += k == 0;
-    n1 += k == 1;
-    n2 += k == 2;
+    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ntF);
+#pragma unroll
+    for (int q = 0; q < kTiers; ++q) n[q] += k == q;
   }
-  sc[0][t] = n0;
-  sc[1][t] = n1;
-  sc[2][t] = n2;
+#pragma unroll
+  for (int q = 0; q < kTiers; ++q) sc[q][t] = n[q];
   __syncthreads();
   for (int o = 1; o < kPartThreads; o <<= 1) {  // inclusive Hillis-Steele scan
-    int a0 = 0, a1 = 0, a2 = 0;
+    int a[kTiers] = {0, 0, 0, 0};
     if (t >= o) {
-      a0 = sc[0][t - o];
-      a1 = sc[1][t - o];
-      a2 = sc[2][t - o];
+#pragma unroll
+      for (int q = 0; q < kTiers; ++q) a[q] = sc[q][t - o];
     }
     __syncthreads();
-    sc[0][t] += a0;
-    sc[1][t] += a1;
-    sc[2][t] += a2;
+#pragma unroll
+    for (int q = 0; q < kTiers; ++q) sc[q][t] += a[q];
     __syncthreads();
   }
-  int w0 = sc[0][t] - n0, w1 = sc[1][t] - n1, w2 = sc[2][t] - n2;  // exclusive offsets
+  int w[kTiers];
+#pragma unroll
+  for (int q = 0; q < kTiers; ++q) w[q] = sc[q][t] - n[q];  // exclusive offsets
   for (int i = lo; i < hi; ++i) {
-    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC);
-    if (k == 0) lists[w0++] = i;
-    if (k == 1) lists[M + w1++] = i;
-    if (k == 2) lists[2 * M + w2++] = i;
+    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ntF);
+#pragma unroll
+    for (int q = 0; q < kTiers; ++q)
+      if (k == q) lists[size_t(q) * M + w[q]++] = i;
   }
   if (t == kPartThreads - 1) {
-    counts[0] = sc[0][t];
-    counts[1] = sc[1][t];
-    counts[2] = sc[2][t];
+#pragma unroll
+    for (int q = 0; q < kTiers; ++q) counts[q] = sc[q][t];
   }
 }
 
@@ -394,6 +395,244 @@ __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
   }
 }
 
+// ----------------------------------------------------------- forward mode
+// Tier F: programs with at most NT constants.  Every value carries NT
+// tangents (d value / d c_q for its program's constants q < NT), propagated
+// with the same local partials as the reverse sweep: one interpreter sweep,
+// no tape and no reverse pass.  A subtree without a constant has zero
+// tangents (the uop's adjoint flags say which operands hold constants), so
+// the tangent work is done only on constant paths.
+template <int K, int NT>
+struct Tangents {
+  typename VecT<float, K>::type q[NT];
+};
+
+template <int K, int D, int NT, class Src>
+__device__ inline typename VecT<float, K>::type run_forward_tangent(
+    const Src& prog, const float* __restrict__ xt, int rstride, int lrow, Tangents<K, NT>& ad) {
+  using V = typename VecT<float, K>::type;
+  using P = Prot<float>;
+  using Dv = Deriv<float>;
+  using O = VOps<float, K>;
+  Slots<V, D> st;
+  Slots<V, D> sd[NT];  // tangents of the pushed values
+  V acc = 0.0f, t = 0.0f, pre = 0.0f;
+  Tangents<K, NT> td;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    ad.q[q] = 0.0f;
+    td.q[q] = 0.0f;
+  }
+  const float* __restrict__ xl = xt + lrow;
+  uint2 cur = prog.at(0);
+  prefetch_operand<float, K>(cur.x, xl, rstride, pre);
+  int pc = 0;
+#pragma unroll 1
+  for (;;) {
+    const uint2 nxt = prog.at(pc + 1);
+    const uint32_t h = cur.x;
+    const uint32_t op = uop_op(h);
+    if (op == UOP_END) break;
+    const uint32_t ld = uop_load(h);
+    const uint32_t sk = uop_src(h);
+    const float c = f32_of(cur.y);
+    if (ld != LD_NONE) {
+      if (h & HDR_PUSH) {
+        st.put(uop_push_slot(h), acc);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) sd[q].put(uop_push_slot(h), ad.q[q]);
+        GG_BRANCH();
+      }
+      if (ld == LD_VAR) {
+        acc = pre;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = 0.0f;
+        GG_BRANCH();
+      }
+      if (ld == LD_CONST) {  // a constant: unit tangent for its own index
+        acc = c;
+        const uint32_t k = uop_load_arg(h);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = uint32_t(q) == k ? 1.0f : 0.0f;
+        GG_BRANCH();
+      }
+      GG_BRANCH();
+    }
+    if (sk == SRC_VAR) {
+      if (ld == LD_VAR) { t = lds_rows<float, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
+      if (ld != LD_VAR) { t = pre; GG_BRANCH(); }
+#pragma unroll
+      for (int q = 0; q < NT; ++q) td.q[q] = 0.0f;
+      GG_BRANCH();
+    }
+    if (sk == SRC_POP) {
+      st.get(uop_src_arg(h), t);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) sd[q].get(uop_src_arg(h), td.q[q]);
+      GG_BRANCH();
+    }
+    if (sk == SRC_CONST) {
+      t = c;
+      const uint32_t k = uop_src_arg(h);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) td.q[q] = uint32_t(q) == k ? 1.0f : 0.0f;
+      GG_BRANCH();
+    }
+    prefetch_operand<float, K>(nxt.x, xl, rstride, pre);
+    const bool live = (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) != 0;  // a constant below
+    if (op == UOP_ADD) {
+      acc = acc + t;
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] + td.q[q];
+      }
+      GG_BRANCH();
+    }
+    if (op == UOP_SUB) {
+      acc = acc - t;
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] - td.q[q];
+      }
+      GG_BRANCH();
+    }
+    if (op == UOP_RSUB) {
+      acc = t - acc;
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = td.q[q] - ad.q[q];
+      }
+      GG_BRANCH();
+    }
+    if (op == UOP_MUL) {
+      if (live) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = t * ad.q[q] + acc * td.q[q];
+      }
+      acc = acc * t;
+      GG_BRANCH();
+    }
+    if (op >= UOP_DIV && !live) {  // no constant below: value only
+      if (op == UOP_DIV) { acc = O::div(acc, t); GG_BRANCH(); }
+      if (op == UOP_RDIV) { acc = O::div(t, acc); GG_BRANCH(); }
+      if (op == UOP_POW) { acc = O::pow(acc, t); GG_BRANCH(); }
+      if (op == UOP_RPOW) { acc = O::pow(t, acc); GG_BRANCH(); }
+      if (op == UOP_SIN) { acc = O::sin(acc); GG_BRANCH(); }
+      if (op == UOP_COS) { acc = O::cos(acc); GG_BRANCH(); }
+      if (op == UOP_SQ) { acc = acc * acc; GG_BRANCH(); }
+      if (op == UOP_SQRT) { acc = O::sqrt(acc); GG_BRANCH(); }
+      if (op == UOP_EXP) { acc = O::exp(acc); GG_BRANCH(); }
+      if (op == UOP_LOG) { acc = O::log(acc); GG_BRANCH(); }
+      GG_BRANCH();
+    }
+    if (op >= UOP_DIV && live) {  // value, local partials, tangents
+      V fa = 1.0f, fs = 1.0f;
+      if (op == UOP_DIV) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::div(acc[j], t[j]);
+          float da, ds;
+          Dv::ddiv(acc[j], t[j], v, da, ds);
+          fa[j] = da;
+          fs[j] = ds;
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_RDIV) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::div(t[j], acc[j]);
+          float da, ds;
+          Dv::ddiv(t[j], acc[j], v, ds, da);
+          fa[j] = da;
+          fs[j] = ds;
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_POW) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::pow_(acc[j], t[j]);
+          float da, ds;
+          Dv::dpow(acc[j], t[j], v, da, ds);
+          fa[j] = da;
+          fs[j] = ds;
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_RPOW) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::pow_(t[j], acc[j]);
+          float da, ds;
+          Dv::dpow(t[j], acc[j], v, ds, da);
+          fa[j] = da;
+          fs[j] = ds;
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_SIN) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = Dv::dsin(acc[j]); acc[j] = P::sin_(acc[j]); }
+        GG_BRANCH();
+      }
+      if (op == UOP_COS) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = Dv::dcos(acc[j]); acc[j] = P::cos_(acc[j]); }
+        GG_BRANCH();
+      }
+      if (op == UOP_SQ) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = 2.0f * acc[j]; acc[j] = acc[j] * acc[j]; }
+        GG_BRANCH();
+      }
+      if (op == UOP_SQRT) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::sqrt_(acc[j]);
+          fa[j] = Dv::dsqrt(acc[j], v);
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_EXP) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const float v = P::exp_(acc[j]);
+          fa[j] = Dv::dexp(acc[j], v);
+          acc[j] = v;
+        }
+        GG_BRANCH();
+      }
+      if (op == UOP_LOG) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) { fa[j] = Dv::dlog(acc[j]); acc[j] = P::log_(acc[j]); }
+        GG_BRANCH();
+      }
+      // unary operators have no source operand: its tangents are zero and
+      // fs is 1, so one formula serves both arities
+      if (op >= UOP_SIN) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q];
+        GG_BRANCH();
+      }
+      if (op < UOP_SIN) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q] + fs * td.q[q];
+        GG_BRANCH();
+      }
+      GG_BRANCH();
+    }
+    cur = nxt;
+    ++pc;
+  }
+  return acc;
+}
+
 // Block prologue shared by the tier kernels: the (span, group slot) of this
 // block with the same XCD-aware numbering as the forward kernel (consecutive
 // items, which share a span and so the same rows of X, land on one XCD and
@@ -476,7 +715,10 @@ __device__ inline void reduce_columns(const float* lacc, int nc, int lane, doubl
 // queue.  SPLIT = true (tier B, few individuals): all W waves share each
 // individual, wave w taking batches w, w+W, ... with its own copy of the
 // accumulators, summed in wave order at the end (bitwise repeatable).
-template <int K, int D, int W, int TC, int NP, bool SPLIT>
+// NT > 0: an individual with at most NT constants is differentiated in
+// forward mode (one sweep, tangents instead of a tape); the others in reverse
+// mode.  One launch serves both kinds, so the queue balances them.
+template <int K, int D, int W, int TC, int NP, bool SPLIT, int NT>
 __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int COPIES = SPLIT ? W : 1;
@@ -529,13 +771,30 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
         const double s1 = p.ab[size_t(i) * 2 + 1];
         const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
-        for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
-          const int lrow = b * BR + lane * K;
-          RegTape<K, TC> tape;
-          const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
-          const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-          const int kv = max(0, min(K, nvalid - lrow));
-          run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
+        if (NT > 0 && nc <= NT) {  // forward mode (wave-uniform)
+          for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
+            const int lrow = b * BR + lane * K;
+            Tangents<K, (NT > 0 ? NT : 1)> ad;
+            const auto v = run_forward_tangent<K, D, (NT > 0 ? NT : 1)>(prog, xs, R, lrow, ad);
+            const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
+            const int kv = max(0, min(K, nvalid - lrow));
+#pragma unroll
+            for (int q = 0; q < (NT > 0 ? NT : 1); ++q) {
+              if (q < nc) {  // wave-uniform
+                const typename VecT<float, K>::type gq = g * ad.q[q];
+                sink.template add<typename VecT<float, K>::type, K>(uint32_t(q), gq, kv);
+              }
+            }
+          }
+        } else {
+          for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
+            const int lrow = b * BR + lane * K;
+            RegTape<K, TC> tape;
+            const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
+            const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
+            const int kv = max(0, min(K, nvalid - lrow));
+            run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
+          }
         }
         reduce_columns<W>(lacc, nc, lane, gmine + size_t(jj) * p.C_max);
         prog = prog_next;
@@ -618,29 +877,34 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
 }
 
 template <int K, int D, int W, int TC, int NP>
-static hipError_t reg_impl1(const TileCfg& c, int CC, bool split, const AdjParams& ap, hipStream_t s) {
+static hipError_t reg_impl1(const TileCfg& c, int CC, bool split, int nt, const AdjParams& ap,
+                            hipStream_t s) {
   const size_t sh = adjoint_reg_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, CC, split ? W : 1);
+  const dim3 grid(ap.n_spans * ap.n_groups), block(W * 64);
   if (split)
-    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, true>), dim3(ap.n_spans * ap.n_groups), dim3(W * 64),
-                       sh, s, ap);
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, true, 0>), grid, block, sh, s, ap);
+  else if (nt == 2)
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false, 2>), grid, block, sh, s, ap);
+  else if (nt == 0)
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false, 0>), grid, block, sh, s, ap);
   else
-    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false>), dim3(ap.n_spans * ap.n_groups),
-                       dim3(W * 64), sh, s, ap);
+    return hipErrorInvalidValue;  // no kernel instantiated for this tangent count
   return hipGetLastError();
 }
 
 // programs of up to 63 tokens use D = 4 (one register pair); longer ones D = 8
 template <int K, int D, int W, int TC>
-static hipError_t reg_impl(const TileCfg& c, int CC, bool split, const AdjParams& ap, hipStream_t s) {
+static hipError_t reg_impl(const TileCfg& c, int CC, bool split, int nt, const AdjParams& ap,
+                           hipStream_t s) {
   if constexpr (D == 4) {
     if (c.NP != 1) return hipErrorInvalidValue;
-    return reg_impl1<K, 4, W, TC, 1>(c, CC, split, ap, s);
+    return reg_impl1<K, 4, W, TC, 1>(c, CC, split, nt, ap, s);
   } else {
     switch (c.NP) {
-      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, split, ap, s);
-      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, split, ap, s);
-      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, split, ap, s);
-      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, split, ap, s);
+      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, split, nt, ap, s);
+      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, split, nt, ap, s);
+      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, split, nt, ap, s);
+      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, split, nt, ap, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -665,30 +929,29 @@ static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, co
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                     int* lists, int* counts, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_partition, dim3(1), dim3(kPartThreads), 0, s, meta, ab, M, a.tc_a,
-                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, lists, counts);
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.need_f ? a.nt_f : 0, lists, counts);
   return hipGetLastError();
 }
 
-// Plain form: per individual i, counts[3i + k] = 1 if it is in tier k, else
-// 0, and list0[0] = 0 (each per-individual launch lists its one individual).
+// Plain form: per individual i, counts[kTiers*i + k] = 1 if it is in tier k,
+// else 0, and list0[0] = 0 (each per-individual launch lists its one individual).
 __global__ __launch_bounds__(256) void k_adj_tier_flags(const ProgMeta* __restrict__ meta,
                                                         const double* __restrict__ ab, int M,
-                                                        int tcA, int tcB, int CC,
+                                                        int tcA, int tcB, int CC, int ntF,
                                                         int* __restrict__ counts,
                                                         int* __restrict__ list0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) list0[0] = 0;
   if (i >= M) return;
-  const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC);
-  counts[3 * i + 0] = k == 0;
-  counts[3 * i + 1] = k == 1;
-  counts[3 * i + 2] = k == 2;
+  const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ntF);
+#pragma unroll
+  for (int q = 0; q < kTiers; ++q) counts[kTiers * i + q] = k == q;
 }
 
 hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                      int* counts, int* list0, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_tier_flags, dim3((M + 255) / 256), dim3(256), 0, s, meta, ab, M, a.tc_a,
-                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, counts, list0);
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.need_f ? a.nt_f : 0, counts, list0);
   return hipGetLastError();
 }
 
@@ -702,13 +965,14 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
                                   gpart, list, count);
   const int CC = a.lane_consts;
   const bool split = tier == 1;  // tier B: few individuals, the waves share each one
+  const int nt = tier == 0 && a.need_f ? a.nt_f : 0;  // forward mode in tier A
   if (c.W != 4) return hipErrorInvalidValue;
-  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, split, ap, s);
-  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, split, ap, s);
-  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, split, ap, s);
-  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, split, ap, s);
-  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, split, ap, s);
-  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, split, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, split, nt, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, split, nt, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, split, nt, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, split, nt, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, split, nt, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, split, nt, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 

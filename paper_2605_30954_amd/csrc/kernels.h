@@ -81,12 +81,14 @@ struct AdjPlan {
   int tape_cap = 1;          // LDS tape entries per wave of tier C
   bool need_b = true;        // some program of this shape may fall in tier B
   bool need_wide = true;     // ... in tier C
+  int nt_f = 2;              // tier A differentiates programs with <= nt_f constants
+  bool need_f = true;        // in forward mode (nt_f tangents per value)
 };
 
-// Tier lists: lists[tier * M + k], counts[tier], tier = 0, 1, 2 (after finalize).
+// Tier lists: lists[tier * M + k], counts[tier], tier = 0 A, 1 B, 2 C (after finalize).
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                     int* lists, int* counts, hipStream_t s);
-// Plain form: counts[3i + tier] = 1 for individual i's tier, list0[0] = 0.
+// Plain form: counts[4i + tier] = 1 for individual i's tier, list0[0] = 0.
 hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                      int* counts, int* list0, hipStream_t s);
 // gradient partials gpart[i][span][C_max] of the individuals list[0 .. *count)
