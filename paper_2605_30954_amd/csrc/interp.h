@@ -57,6 +57,26 @@ __device__ inline typename VecT<T, K>::type lds_rows(const float* __restrict__ p
   return v;
 }
 
+// A wave-uniform binary32 value (in an SGPR) copied to every element of a
+// K-vector with one VALU move per element (the compiler would otherwise pair
+// the elements into 64-bit moves fed by a chain of scalar copies).
+template <typename T, int K>
+__device__ inline typename VecT<T, K>::type bcast(float c) {
+  typename VecT<T, K>::type v;
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      float x;
+      asm("v_mov_b32 %0, %1" : "=v"(x) : "s"(c));
+      v[j] = x;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = T(c);
+  }
+  return v;
+}
+
 // D register slots, addressed by a wave-uniform slot number.
 template <typename V, int D>
 struct Slots {
@@ -129,7 +149,7 @@ struct UopRegs {
 #pragma unroll
     for (int e = 0; e < NP; ++e) {
       const int idx = e * 64 + lane;
-      uint2 u = make_uint2(uint32_t(UOP_END), 0u);
+      uint2 u = make_uint2(UOP_END_HDR, 0u);
       if (idx < n) u = prog[idx];
       lo[e] = u.x;
       hi[e] = u.y;
@@ -142,7 +162,7 @@ struct UopRegs {
                         uint32_t(__builtin_amdgcn_readlane(int(hi[0]), l)));
     } else {
       const int q = pc >> 6;
-      uint32_t a = uint32_t(UOP_END), b = 0u;
+      uint32_t a = UOP_END_HDR, b = 0u;
 #pragma unroll
       for (int e = 0; e < NP; ++e) {
         if (q == e) {
@@ -247,17 +267,75 @@ struct VOps {
 #undef GG_MAP2
 };
 
-// Operand prefetch: the first variable operand of uop header h (its load
-// prefix if that is a variable, else its source if that is a variable) is read
-// from the row tile into `pre`, so that the LDS latency overlaps the work of
-// the uop before it.
+// Operand prefetch: the first variable operand of uop header h (field var1)
+// is read from the row tile into `pre`, so that the LDS latency overlaps the
+// work of the uop before it.
 template <typename T, int K>
 __device__ inline void prefetch_operand(uint32_t h, const float* __restrict__ xl, int rstride,
                                         typename VecT<T, K>::type& pre) {
-  if (uop_load(h) == LD_VAR) { pre = lds_rows<T, K>(xl + uop_load_arg(h) * rstride); GG_BRANCH(); }
-  if (uop_load(h) != LD_VAR && uop_src(h) == SRC_VAR) {
-    pre = lds_rows<T, K>(xl + uop_src_arg(h) * rstride);
+  if (h & U_V1) {
+    pre = lds_rows<T, K>(xl + uop_var1(h) * rstride);
     GG_BRANCH();
+  }
+}
+
+// Operand stage shared by the interpreters: push, load prefix and the src
+// operand of uop h.  Every header bit is tested once (a condition the compiler
+// could share between blocks would be kept as a lane mask and cost extra
+// instructions per test).  On return acc holds the acc operand and t the src
+// operand; `pre` holds the uop's first variable operand (read one uop ahead).
+template <typename T, int K, int D>
+__device__ inline void operand_stage(uint32_t h, float c, const float* __restrict__ xl,
+                                     int rstride, typename VecT<T, K>::type& acc,
+                                     typename VecT<T, K>::type& t,
+                                     const typename VecT<T, K>::type& pre,
+                                     Slots<typename VecT<T, K>::type, D>& st) {
+  if (h & (U_LDV | U_LDC)) {  // first leaf of a subtree (after pushing the pending value)
+    if (h & HDR_PUSH) {
+      st.put(uop_push_slot(h), acc);
+      GG_BRANCH();
+    }
+    if (h & U_LDV) {
+      acc = pre;
+      GG_BRANCH();
+    } else {
+      acc = bcast<T, K>(c);
+      GG_BRANCH();
+    }
+    GG_BRANCH();
+  }
+  if (h & U_TPRE) {
+    t = pre;
+    GG_BRANCH();
+  } else if (h & U_SC) {
+    t = bcast<T, K>(c);
+    GG_BRANCH();
+  } else if (h & U_TX2) {
+    t = lds_rows<T, K>(xl + uop_arg2(h) * rstride);
+    GG_BRANCH();
+  } else if (h & U_SP) {
+    st.get(uop_arg2(h), t);
+    GG_BRANCH();
+  }
+}
+
+// Value of a non-cheap operator on K rows (NOP leaves acc unchanged).
+template <typename T, int K>
+__device__ inline void op_value(uint32_t op, typename VecT<T, K>::type& acc,
+                                const typename VecT<T, K>::type& t) {
+  using O = VOps<T, K>;
+  switch (op) {
+    case UOP_DIV: acc = O::div(acc, t); GG_BRANCH(); break;
+    case UOP_RDIV: acc = O::div(t, acc); GG_BRANCH(); break;
+    case UOP_POW: acc = O::pow(acc, t); GG_BRANCH(); break;
+    case UOP_RPOW: acc = O::pow(t, acc); GG_BRANCH(); break;
+    case UOP_SIN: acc = O::sin(acc); GG_BRANCH(); break;
+    case UOP_COS: acc = O::cos(acc); GG_BRANCH(); break;
+    case UOP_SQ: acc = acc * acc; GG_BRANCH(); break;
+    case UOP_SQRT: acc = O::sqrt(acc); GG_BRANCH(); break;
+    case UOP_EXP: acc = O::exp(acc); GG_BRANCH(); break;
+    case UOP_LOG: acc = O::log(acc); GG_BRANCH(); break;
+    default: GG_BRANCH(); break;  // NOP
   }
 }
 
@@ -265,6 +343,11 @@ __device__ inline void prefetch_operand(uint32_t h, const float* __restrict__ xl
 //   prog    uop source of this individual (UopMem or UopRegs)
 //   xt      LDS row tile: feature k, row r at xt[k*rstride + r]
 //   lrow    this lane's first row within the tile (multiple of K)
+//
+// The scalar unit is shared by the four SIMDs of a compute unit and its
+// instructions (field tests, branches) bound the interpreter's rate, so every
+// decision is a single-bit test of the header, the tests are nested (a uop
+// pays only for the path it takes) and the END test sits at the loop latch.
 template <typename T, int K, int D, class Src>
 __device__ inline typename VecT<T, K>::type run_program(const Src& prog,
                                                         const float* __restrict__ xt, int rstride,
@@ -278,62 +361,40 @@ __device__ inline typename VecT<T, K>::type run_program(const Src& prog,
   prefetch_operand<T, K>(cur.x, xl, rstride, pre);
   int pc = 0;
 #pragma unroll 1
-  for (;;) {
+  while (!(cur.x & U_END)) {
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
-    const uint32_t op = uop_op(h);
-    if (op == UOP_END) break;
-    const uint32_t ld = uop_load(h);
-    const uint32_t sk = uop_src(h);
-    const T c = T(f32_of(cur.y));
-    // load prefix: the first leaf of a subtree (after pushing the pending value);
-    // the first variable operand was read one uop ahead into `pre`
-    if (ld != LD_NONE) {
-      if (h & HDR_PUSH) { st.put(uop_push_slot(h), acc); GG_BRANCH(); }
-      if (ld == LD_VAR) { acc = pre; GG_BRANCH(); }
-      if (ld == LD_CONST) { acc = c; GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (sk == SRC_VAR) {
-      if (ld == LD_VAR) { t = lds_rows<T, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
-      if (ld != LD_VAR) { t = pre; GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (sk == SRC_POP) { st.get(uop_src_arg(h), t); GG_BRANCH(); }
+    const float c = f32_of(cur.y);
+    operand_stage<T, K, D>(h, c, xl, rstride, acc, t, pre, st);
     // `pre` is consumed: start reading the next uop's first variable operand
     prefetch_operand<T, K>(nxt.x, xl, rstride, pre);
-    if (op <= UOP_MUL) {
-      if (sk == SRC_CONST) {  // the constant stays a scalar operand
-        if (op == UOP_ADD) { acc = acc + c; GG_BRANCH(); }
-        if (op == UOP_SUB) { acc = acc - c; GG_BRANCH(); }
-        if (op == UOP_RSUB) { acc = c - acc; GG_BRANCH(); }
-        if (op == UOP_MUL) { acc = acc * c; GG_BRANCH(); }
+    if (h & U_CHEAP) {  // ADD 1, SUB 2, RSUB 3, MUL 4: bit 2 = MUL, else bits 0-1
+      if (h & 4u) {
+        acc = acc * t;
         GG_BRANCH();
-      }
-      if (sk == SRC_VAR || sk == SRC_POP) {
-        if (op == UOP_ADD) { acc = acc + t; GG_BRANCH(); }
-        if (op == UOP_SUB) { acc = acc - t; GG_BRANCH(); }
-        if (op == UOP_RSUB) { acc = t - acc; GG_BRANCH(); }
-        if (op == UOP_MUL) { acc = acc * t; GG_BRANCH(); }
+      } else if (h & 2u) {
+        if (h & 1u) { acc = t - acc; GG_BRANCH(); }
+        else { acc = acc - t; GG_BRANCH(); }
+        GG_BRANCH();
+      } else {
+        acc = acc + t;
         GG_BRANCH();
       }
       GG_BRANCH();
-    }
-    if (op >= UOP_DIV && op <= UOP_RPOW) {
-      if (sk == SRC_CONST) { t = c; GG_BRANCH(); }
-      if (op == UOP_DIV) { acc = O::div(acc, t); GG_BRANCH(); }
-      if (op == UOP_RDIV) { acc = O::div(t, acc); GG_BRANCH(); }
-      if (op == UOP_POW) { acc = O::pow(acc, t); GG_BRANCH(); }
-      if (op == UOP_RPOW) { acc = O::pow(t, acc); GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (op >= UOP_SIN) {
-      if (op == UOP_SIN) { acc = O::sin(acc); GG_BRANCH(); }
-      if (op == UOP_COS) { acc = O::cos(acc); GG_BRANCH(); }
-      if (op == UOP_SQ) { acc = acc * acc; GG_BRANCH(); }
-      if (op == UOP_SQRT) { acc = O::sqrt(acc); GG_BRANCH(); }
-      if (op == UOP_EXP) { acc = O::exp(acc); GG_BRANCH(); }
-      if (op == UOP_LOG) { acc = O::log(acc); GG_BRANCH(); }
+    } else {
+      switch (uop_op(h)) {
+        case UOP_DIV: acc = O::div(acc, t); GG_BRANCH(); break;
+        case UOP_RDIV: acc = O::div(t, acc); GG_BRANCH(); break;
+        case UOP_POW: acc = O::pow(acc, t); GG_BRANCH(); break;
+        case UOP_RPOW: acc = O::pow(t, acc); GG_BRANCH(); break;
+        case UOP_SIN: acc = O::sin(acc); GG_BRANCH(); break;
+        case UOP_COS: acc = O::cos(acc); GG_BRANCH(); break;
+        case UOP_SQ: acc = acc * acc; GG_BRANCH(); break;
+        case UOP_SQRT: acc = O::sqrt(acc); GG_BRANCH(); break;
+        case UOP_EXP: acc = O::exp(acc); GG_BRANCH(); break;
+        case UOP_LOG: acc = O::log(acc); GG_BRANCH(); break;
+        default: GG_BRANCH(); break;  // NOP
+      }
       GG_BRANCH();
     }
     cur = nxt;

@@ -174,145 +174,147 @@ struct RegTape {
   }
 };
 
+// Value and local partials of a non-cheap operator on K rows: fa = d result /
+// d acc operand, fs = d result / d src operand (unary operators leave fs
+// untouched).  NOP leaves acc and the partials as they are.
+template <int K>
+__device__ inline void op_partials(uint32_t op, typename VecT<float, K>::type& acc,
+                                   const typename VecT<float, K>::type& t,
+                                   typename VecT<float, K>::type& fa,
+                                   typename VecT<float, K>::type& fs) {
+  using P = Prot<float>;
+  using Dv = Deriv<float>;
+  switch (op) {
+    case UOP_DIV:
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = P::div(acc[j], t[j]);
+        float da, ds;
+        Dv::ddiv(acc[j], t[j], v, da, ds);
+        acc[j] = v; fa[j] = da; fs[j] = ds;
+      }
+      GG_BRANCH();
+      break;
+    case UOP_RDIV:
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = P::div(t[j], acc[j]);
+        float da, ds;
+        Dv::ddiv(t[j], acc[j], v, ds, da);
+        acc[j] = v; fa[j] = da; fs[j] = ds;
+      }
+      GG_BRANCH();
+      break;
+    case UOP_POW:
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = P::pow_(acc[j], t[j]);
+        float da, ds;
+        Dv::dpow(acc[j], t[j], v, da, ds);
+        acc[j] = v; fa[j] = da; fs[j] = ds;
+      }
+      GG_BRANCH();
+      break;
+    case UOP_RPOW:
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = P::pow_(t[j], acc[j]);
+        float da, ds;
+        Dv::dpow(t[j], acc[j], v, ds, da);
+        acc[j] = v; fa[j] = da; fs[j] = ds;
+      }
+      GG_BRANCH();
+      break;
+    case UOP_SIN:
+#pragma unroll
+      for (int j = 0; j < K; ++j) { fa[j] = Dv::dsin(acc[j]); acc[j] = P::sin_(acc[j]); }
+      GG_BRANCH();
+      break;
+    case UOP_COS:
+#pragma unroll
+      for (int j = 0; j < K; ++j) { fa[j] = Dv::dcos(acc[j]); acc[j] = P::cos_(acc[j]); }
+      GG_BRANCH();
+      break;
+    case UOP_SQ:
+#pragma unroll
+      for (int j = 0; j < K; ++j) { fa[j] = 2.0f * acc[j]; acc[j] = acc[j] * acc[j]; }
+      GG_BRANCH();
+      break;
+    case UOP_SQRT:
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = P::sqrt_(acc[j]);
+        fa[j] = Dv::dsqrt(acc[j], v);
+        acc[j] = v;
+      }
+      GG_BRANCH();
+      break;
+    case UOP_EXP:
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float v = P::exp_(acc[j]);
+        fa[j] = Dv::dexp(acc[j], v);
+        acc[j] = v;
+      }
+      GG_BRANCH();
+      break;
+    case UOP_LOG:
+#pragma unroll
+      for (int j = 0; j < K; ++j) { fa[j] = Dv::dlog(acc[j]); acc[j] = P::log_(acc[j]); }
+      GG_BRANCH();
+      break;
+    default:
+      GG_BRANCH();
+      break;
+  }
+}
+
 // Forward sweep with the tape (float nodes).  Same values as run_program; in
 // addition each uop stores d(result)/d(acc operand) and d(result)/d(src
-// operand) when the reverse sweep needs them (tape_acc / tape_src).
+// operand) when the reverse sweep needs them (tape_acc / tape_src), acc's
+// entry first.
 template <int K, int D, class Src, class Tape>
 __device__ inline typename VecT<float, K>::type run_forward_taped(
     const Src& prog, const float* __restrict__ xt, int rstride, int lrow, Tape& tape) {
   using V = typename VecT<float, K>::type;
-  using P = Prot<float>;
-  using Dv = Deriv<float>;
-  using O = VOps<float, K>;
   Slots<V, D> st;
-  V acc = 0.0f, t = 0.0f, fa = 1.0f, fs = 1.0f, pre = 0.0f;
+  V acc = 0.0f, t = 0.0f, pre = 0.0f;
   const float* __restrict__ xl = xt + lrow;
   uint2 cur = prog.at(0);
   prefetch_operand<float, K>(cur.x, xl, rstride, pre);
   int pc = 0, tp = 0;
 #pragma unroll 1
-  for (;;) {
+  while (!(cur.x & U_END)) {
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
-    const uint32_t op = uop_op(h);
-    if (op == UOP_END) break;
-    const uint32_t ld = uop_load(h);
-    const uint32_t sk = uop_src(h);
-    const float c = f32_of(cur.y);
-    if (ld != LD_NONE) {
-      if (h & HDR_PUSH) { st.put(uop_push_slot(h), acc); GG_BRANCH(); }
-      if (ld == LD_VAR) { acc = pre; GG_BRANCH(); }
-      if (ld == LD_CONST) { acc = c; GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (sk == SRC_VAR) {
-      if (ld == LD_VAR) { t = lds_rows<float, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
-      if (ld != LD_VAR) { t = pre; GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (sk == SRC_POP) { st.get(uop_src_arg(h), t); GG_BRANCH(); }
+    operand_stage<float, K, D>(h, f32_of(cur.y), xl, rstride, acc, t, pre, st);
     prefetch_operand<float, K>(nxt.x, xl, rstride, pre);  // next uop's first variable
-    if (sk == SRC_CONST) { t = c; GG_BRANCH(); }
-    if (op == UOP_ADD) { acc = acc + t; GG_BRANCH(); }
-    if (op == UOP_SUB) { acc = acc - t; GG_BRANCH(); }
-    if (op == UOP_RSUB) { acc = t - acc; GG_BRANCH(); }
-    if (op == UOP_MUL) { fa = t; fs = acc; acc = acc * t; GG_BRANCH(); }
-    if (op >= UOP_DIV && !(h & (HDR_ADJ_ACC | HDR_ADJ_SRC))) {  // no constant below: value only
-      if (op == UOP_DIV) { acc = O::div(acc, t); GG_BRANCH(); }
-      if (op == UOP_RDIV) { acc = O::div(t, acc); GG_BRANCH(); }
-      if (op == UOP_POW) { acc = O::pow(acc, t); GG_BRANCH(); }
-      if (op == UOP_RPOW) { acc = O::pow(t, acc); GG_BRANCH(); }
-      if (op == UOP_SIN) { acc = O::sin(acc); GG_BRANCH(); }
-      if (op == UOP_COS) { acc = O::cos(acc); GG_BRANCH(); }
-      if (op == UOP_SQ) { acc = acc * acc; GG_BRANCH(); }
-      if (op == UOP_SQRT) { acc = O::sqrt(acc); GG_BRANCH(); }
-      if (op == UOP_EXP) { acc = O::exp(acc); GG_BRANCH(); }
-      if (op == UOP_LOG) { acc = O::log(acc); GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (op >= UOP_DIV && (h & (HDR_ADJ_ACC | HDR_ADJ_SRC))) {  // value and local partials
-      if (op == UOP_DIV) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::div(acc[j], t[j]);
-          float da, ds;
-          Dv::ddiv(acc[j], t[j], v, da, ds);
-          acc[j] = v; fa[j] = da; fs[j] = ds;
-        }
+    if (h & U_CHEAP) {  // ADD 1, SUB 2, RSUB 3, MUL 4
+      if (h & 4u) {
+        // d(acc*t)/d acc = t (a constant src needs no tape), d/d t = acc
+        if ((h & (HDR_ADJ_ACC | U_SC)) == HDR_ADJ_ACC) { tape.put(tp, t); ++tp; GG_BRANCH(); }
+        if (h & HDR_ADJ_SRC) { tape.put(tp, acc); ++tp; GG_BRANCH(); }
+        acc = acc * t;
         GG_BRANCH();
-      }
-      if (op == UOP_RDIV) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::div(t[j], acc[j]);
-          float da, ds;
-          Dv::ddiv(t[j], acc[j], v, ds, da);
-          acc[j] = v; fa[j] = da; fs[j] = ds;
-        }
+      } else if (h & 2u) {
+        if (h & 1u) { acc = t - acc; GG_BRANCH(); }
+        else { acc = acc - t; GG_BRANCH(); }
         GG_BRANCH();
-      }
-      if (op == UOP_POW) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::pow_(acc[j], t[j]);
-          float da, ds;
-          Dv::dpow(acc[j], t[j], v, da, ds);
-          acc[j] = v; fa[j] = da; fs[j] = ds;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_RPOW) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::pow_(t[j], acc[j]);
-          float da, ds;
-          Dv::dpow(t[j], acc[j], v, ds, da);
-          acc[j] = v; fa[j] = da; fs[j] = ds;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_SIN) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = Dv::dsin(acc[j]); acc[j] = P::sin_(acc[j]); }
-        GG_BRANCH();
-      }
-      if (op == UOP_COS) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = Dv::dcos(acc[j]); acc[j] = P::cos_(acc[j]); }
-        GG_BRANCH();
-      }
-      if (op == UOP_SQ) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = 2.0f * acc[j]; acc[j] = acc[j] * acc[j]; }
-        GG_BRANCH();
-      }
-      if (op == UOP_SQRT) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::sqrt_(acc[j]);
-          fa[j] = Dv::dsqrt(acc[j], v);
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_EXP) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::exp_(acc[j]);
-          fa[j] = Dv::dexp(acc[j], v);
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_LOG) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = Dv::dlog(acc[j]); acc[j] = P::log_(acc[j]); }
+      } else {
+        acc = acc + t;
         GG_BRANCH();
       }
       GG_BRANCH();
+    } else if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {  // a constant below: value and partials
+      V fa = 1.0f, fs = 1.0f;
+      op_partials<K>(uop_op(h), acc, t, fa, fs);
+      if ((h & HDR_ADJ_ACC) && uop_op(h) != UOP_NOP) { tape.put(tp, fa); ++tp; GG_BRANCH(); }
+      if (h & HDR_ADJ_SRC) { tape.put(tp, fs); ++tp; GG_BRANCH(); }
+      GG_BRANCH();
+    } else {
+      op_value<float, K>(uop_op(h), acc, t);
+      GG_BRANCH();
     }
-    if (tape_acc(h)) { tape.put(tp, fa); ++tp; GG_BRANCH(); }
-    if (tape_src(h)) { tape.put(tp, fs); ++tp; GG_BRANCH(); }
     cur = nxt;
     ++pc;
   }
@@ -358,7 +360,8 @@ struct LaneSink {
 };
 
 // Reverse sweep.  g = adjoint of the program output per row (zero on padding
-// rows); kv = valid rows of this lane.
+// rows); kv = valid rows of this lane.  Uops with no constant below them and
+// no push are skipped with one test.
 template <int K, int D, class Src, class Tape, class Sink>
 __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
                                    typename VecT<float, K>::type g, const Tape& tape, Sink& sink,
@@ -373,25 +376,44 @@ __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
     const uint2 u = nxt;
     nxt = prog.at(pc > 0 ? pc - 1 : 0);
     const uint32_t h = u.x;
-    const uint32_t op = uop_op(h);
-    const uint32_t sk = uop_src(h);
-    const int ts = tape_src(h), ta = tape_acc(h);
-    if (h & HDR_ADJ_SRC) {  // d result / d src
-      if (ts) { --tp; gsrc = g * tape.get(tp); GG_BRANCH(); }
-      if (!ts && op == UOP_SUB) { gsrc = -g; GG_BRANCH(); }
-      if (!ts && op != UOP_SUB) { gsrc = g; GG_BRANCH(); }  // ADD, RSUB: +1
-      if (sk == SRC_CONST) { sink.template add<V, K>(uop_src_arg(h), gsrc, kv); GG_BRANCH(); }
-      if (sk == SRC_POP) { gs.put(uop_src_arg(h), gsrc); GG_BRANCH(); }
+    if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC | HDR_PUSH)) {
+      if (h & HDR_ADJ_SRC) {  // d result / d src
+        if (h & U_CHEAP) {
+          if (h & 4u) { --tp; gsrc = g * tape.get(tp); GG_BRANCH(); }       // MUL
+          else if ((h & 3u) == 2u) { gsrc = -g; GG_BRANCH(); }              // SUB
+          else { gsrc = g; GG_BRANCH(); }                                   // ADD, RSUB
+          GG_BRANCH();
+        } else {
+          --tp;
+          gsrc = g * tape.get(tp);  // DIV, RDIV, POW, RPOW
+          GG_BRANCH();
+        }
+        if (h & U_SC) { sink.template add<V, K>(uop_arg2(h), gsrc, kv); GG_BRANCH(); }
+        else if (h & U_SP) { gs.put(uop_arg2(h), gsrc); GG_BRANCH(); }
+        GG_BRANCH();
+      }
+      if (h & HDR_ADJ_ACC) {  // d result / d acc operand
+        if (h & U_CHEAP) {
+          if (h & 4u) {  // MUL: the src factor (a constant src is the payload)
+            if (h & U_SC) { g = g * f32_of(u.y); GG_BRANCH(); }
+            else { --tp; g = g * tape.get(tp); GG_BRANCH(); }
+            GG_BRANCH();
+          } else if ((h & 3u) == 3u) {
+            g = -g;  // RSUB
+            GG_BRANCH();
+          }
+          GG_BRANCH();
+        } else if (uop_op(h) != UOP_NOP) {
+          --tp;
+          g = g * tape.get(tp);
+          GG_BRANCH();
+        }
+        if (h & U_LDC) { sink.template add<V, K>(uop_arg2(h), g, kv); GG_BRANCH(); }
+        GG_BRANCH();
+      }
+      if (h & HDR_PUSH) { gs.get(uop_push_slot(h), g); GG_BRANCH(); }
       GG_BRANCH();
     }
-    if (h & HDR_ADJ_ACC) {  // d result / d acc operand
-      if (ta) { --tp; g = g * tape.get(tp); GG_BRANCH(); }
-      if (!ta && op == UOP_RSUB) { g = -g; GG_BRANCH(); }
-      if (!ta && op == UOP_MUL) { g = g * f32_of(u.y); GG_BRANCH(); }  // constant factor
-      if (uop_load(h) == LD_CONST) { sink.template add<V, K>(uop_load_arg(h), g, kv); GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (h & HDR_PUSH) { gs.get(uop_push_slot(h), g); GG_BRANCH(); }
   }
 }
 
@@ -411,9 +433,6 @@ template <int K, int D, int NT, class Src>
 __device__ inline typename VecT<float, K>::type run_forward_tangent(
     const Src& prog, const float* __restrict__ xt, int rstride, int lrow, Tangents<K, NT>& ad) {
   using V = typename VecT<float, K>::type;
-  using P = Prot<float>;
-  using Dv = Deriv<float>;
-  using O = VOps<float, K>;
   Slots<V, D> st;
   Slots<V, D> sd[NT];  // tangents of the pushed values
   V acc = 0.0f, t = 0.0f, pre = 0.0f;
@@ -428,203 +447,108 @@ __device__ inline typename VecT<float, K>::type run_forward_tangent(
   prefetch_operand<float, K>(cur.x, xl, rstride, pre);
   int pc = 0;
 #pragma unroll 1
-  for (;;) {
+  while (!(cur.x & U_END)) {
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
-    const uint32_t op = uop_op(h);
-    if (op == UOP_END) break;
-    const uint32_t ld = uop_load(h);
-    const uint32_t sk = uop_src(h);
     const float c = f32_of(cur.y);
-    if (ld != LD_NONE) {
+    // operands and their tangents (a constant: unit tangent for its own index)
+    if (h & (U_LDV | U_LDC)) {
       if (h & HDR_PUSH) {
         st.put(uop_push_slot(h), acc);
 #pragma unroll
         for (int q = 0; q < NT; ++q) sd[q].put(uop_push_slot(h), ad.q[q]);
         GG_BRANCH();
       }
-      if (ld == LD_VAR) {
+      if (h & U_LDV) {
         acc = pre;
 #pragma unroll
         for (int q = 0; q < NT; ++q) ad.q[q] = 0.0f;
         GG_BRANCH();
-      }
-      if (ld == LD_CONST) {  // a constant: unit tangent for its own index
-        acc = c;
-        const uint32_t k = uop_load_arg(h);
+      } else {
+        acc = bcast<float, K>(c);
+        const uint32_t k = uop_arg2(h);
 #pragma unroll
         for (int q = 0; q < NT; ++q) ad.q[q] = uint32_t(q) == k ? 1.0f : 0.0f;
         GG_BRANCH();
       }
       GG_BRANCH();
     }
-    if (sk == SRC_VAR) {
-      if (ld == LD_VAR) { t = lds_rows<float, K>(xl + uop_src_arg(h) * rstride); GG_BRANCH(); }
-      if (ld != LD_VAR) { t = pre; GG_BRANCH(); }
+    if (h & U_TPRE) {
+      t = pre;
 #pragma unroll
       for (int q = 0; q < NT; ++q) td.q[q] = 0.0f;
       GG_BRANCH();
-    }
-    if (sk == SRC_POP) {
-      st.get(uop_src_arg(h), t);
-#pragma unroll
-      for (int q = 0; q < NT; ++q) sd[q].get(uop_src_arg(h), td.q[q]);
-      GG_BRANCH();
-    }
-    if (sk == SRC_CONST) {
-      t = c;
-      const uint32_t k = uop_src_arg(h);
+    } else if (h & U_SC) {
+      t = bcast<float, K>(c);
+      const uint32_t k = uop_arg2(h);
 #pragma unroll
       for (int q = 0; q < NT; ++q) td.q[q] = uint32_t(q) == k ? 1.0f : 0.0f;
       GG_BRANCH();
+    } else if (h & U_TX2) {
+      t = lds_rows<float, K>(xl + uop_arg2(h) * rstride);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) td.q[q] = 0.0f;
+      GG_BRANCH();
+    } else if (h & U_SP) {
+      st.get(uop_arg2(h), t);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) sd[q].get(uop_arg2(h), td.q[q]);
+      GG_BRANCH();
     }
     prefetch_operand<float, K>(nxt.x, xl, rstride, pre);
-    const bool live = (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) != 0;  // a constant below
-    if (op == UOP_ADD) {
-      acc = acc + t;
-      if (live) {
+    if (h & U_CHEAP) {  // ADD 1, SUB 2, RSUB 3, MUL 4
+      if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {
+        if (h & 4u) {
 #pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] + td.q[q];
+          for (int q = 0; q < NT; ++q) ad.q[q] = t * ad.q[q] + acc * td.q[q];
+          acc = acc * t;
+          GG_BRANCH();
+        } else if (h & 2u) {
+          if (h & 1u) {
+            acc = t - acc;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) ad.q[q] = td.q[q] - ad.q[q];
+            GG_BRANCH();
+          } else {
+            acc = acc - t;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] - td.q[q];
+            GG_BRANCH();
+          }
+          GG_BRANCH();
+        } else {
+          acc = acc + t;
+#pragma unroll
+          for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] + td.q[q];
+          GG_BRANCH();
+        }
+        GG_BRANCH();
+      } else {  // no constant below: value only
+        if (h & 4u) { acc = acc * t; GG_BRANCH(); }
+        else if (h & 2u) {
+          if (h & 1u) { acc = t - acc; GG_BRANCH(); }
+          else { acc = acc - t; GG_BRANCH(); }
+          GG_BRANCH();
+        } else { acc = acc + t; GG_BRANCH(); }
+        GG_BRANCH();
       }
       GG_BRANCH();
-    }
-    if (op == UOP_SUB) {
-      acc = acc - t;
-      if (live) {
+    } else if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {  // value, local partials, tangents
+      V fa = 1.0f, fs = 0.0f;
+      op_partials<K>(uop_op(h), acc, t, fa, fs);
+      // a unary operator has no src operand: fs stays 0 and td is not used
+      if (h & (U_TPRE | U_SC | U_TX2 | U_SP)) {
 #pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] - td.q[q];
-      }
-      GG_BRANCH();
-    }
-    if (op == UOP_RSUB) {
-      acc = t - acc;
-      if (live) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = td.q[q] - ad.q[q];
-      }
-      GG_BRANCH();
-    }
-    if (op == UOP_MUL) {
-      if (live) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = t * ad.q[q] + acc * td.q[q];
-      }
-      acc = acc * t;
-      GG_BRANCH();
-    }
-    if (op >= UOP_DIV && !live) {  // no constant below: value only
-      if (op == UOP_DIV) { acc = O::div(acc, t); GG_BRANCH(); }
-      if (op == UOP_RDIV) { acc = O::div(t, acc); GG_BRANCH(); }
-      if (op == UOP_POW) { acc = O::pow(acc, t); GG_BRANCH(); }
-      if (op == UOP_RPOW) { acc = O::pow(t, acc); GG_BRANCH(); }
-      if (op == UOP_SIN) { acc = O::sin(acc); GG_BRANCH(); }
-      if (op == UOP_COS) { acc = O::cos(acc); GG_BRANCH(); }
-      if (op == UOP_SQ) { acc = acc * acc; GG_BRANCH(); }
-      if (op == UOP_SQRT) { acc = O::sqrt(acc); GG_BRANCH(); }
-      if (op == UOP_EXP) { acc = O::exp(acc); GG_BRANCH(); }
-      if (op == UOP_LOG) { acc = O::log(acc); GG_BRANCH(); }
-      GG_BRANCH();
-    }
-    if (op >= UOP_DIV && live) {  // value, local partials, tangents
-      V fa = 1.0f, fs = 1.0f;
-      if (op == UOP_DIV) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::div(acc[j], t[j]);
-          float da, ds;
-          Dv::ddiv(acc[j], t[j], v, da, ds);
-          fa[j] = da;
-          fs[j] = ds;
-          acc[j] = v;
-        }
+        for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q] + fs * td.q[q];
         GG_BRANCH();
-      }
-      if (op == UOP_RDIV) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::div(t[j], acc[j]);
-          float da, ds;
-          Dv::ddiv(t[j], acc[j], v, ds, da);
-          fa[j] = da;
-          fs[j] = ds;
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_POW) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::pow_(acc[j], t[j]);
-          float da, ds;
-          Dv::dpow(acc[j], t[j], v, da, ds);
-          fa[j] = da;
-          fs[j] = ds;
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_RPOW) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::pow_(t[j], acc[j]);
-          float da, ds;
-          Dv::dpow(t[j], acc[j], v, ds, da);
-          fa[j] = da;
-          fs[j] = ds;
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_SIN) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = Dv::dsin(acc[j]); acc[j] = P::sin_(acc[j]); }
-        GG_BRANCH();
-      }
-      if (op == UOP_COS) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = Dv::dcos(acc[j]); acc[j] = P::cos_(acc[j]); }
-        GG_BRANCH();
-      }
-      if (op == UOP_SQ) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = 2.0f * acc[j]; acc[j] = acc[j] * acc[j]; }
-        GG_BRANCH();
-      }
-      if (op == UOP_SQRT) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::sqrt_(acc[j]);
-          fa[j] = Dv::dsqrt(acc[j], v);
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_EXP) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const float v = P::exp_(acc[j]);
-          fa[j] = Dv::dexp(acc[j], v);
-          acc[j] = v;
-        }
-        GG_BRANCH();
-      }
-      if (op == UOP_LOG) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) { fa[j] = Dv::dlog(acc[j]); acc[j] = P::log_(acc[j]); }
-        GG_BRANCH();
-      }
-      // unary operators have no source operand: its tangents are zero and
-      // fs is 1, so one formula serves both arities
-      if (op >= UOP_SIN) {
+      } else {
 #pragma unroll
         for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q];
         GG_BRANCH();
       }
-      if (op < UOP_SIN) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q] + fs * td.q[q];
-        GG_BRANCH();
-      }
+      GG_BRANCH();
+    } else {
+      op_value<float, K>(uop_op(h), acc, t);
       GG_BRANCH();
     }
     cur = nxt;

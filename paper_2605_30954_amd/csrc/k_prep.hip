@@ -151,7 +151,7 @@ struct Emitter {
   __device__ inline void emit(uint32_t hdr, uint32_t payload) {
     if (push_pending) {
       if (uop_load(hdr) == LD_NONE) bad = true;  // a pushed subtree starts with a load
-      hdr |= HDR_PUSH | (push_slot << 10);
+      hdr = with_push(hdr, push_slot);
       push_pending = false;
     }
     if (n >= cap) {
@@ -366,13 +366,13 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
   }
   bad = bad || E.bad;
   if (bad) {
-    out[0] = make_uint2(UOP_END, 0);
-    out[1] = make_uint2(UOP_END, 0);
+    out[0] = make_uint2(UOP_END_HDR, 0);
+    out[1] = make_uint2(UOP_END_HDR, 0);
     pm.status = 2;
     pm.n_uops = 1;
   } else {
-    out[E.n] = make_uint2(UOP_END, 0);
-    out[E.n + 1] = make_uint2(UOP_END, 0);
+    out[E.n] = make_uint2(UOP_END_HDR, 0);
+    out[E.n + 1] = make_uint2(UOP_END_HDR, 0);
     pm.n_uops = E.n + 1;
     pm.slots = maxsp;
     pm.n_tape = E.tape;

@@ -12,16 +12,27 @@
 // result: each subtree is computed by the same operations on the same inputs.
 //
 // One uop = uint2 {hdr, payload}; payload carries a constant's float bits.
-//   hdr[0:5)   op (UOP_*)
-//   hdr[5:7)   src kind: 0 none (unary), 1 variable, 2 constant, 3 pop S[slot]
-//   hdr[7:9)   load prefix: 0 none, 1 variable, 2 constant (acc <- terminal
-//              before the operator runs; used for the first leaf of a subtree)
-//   hdr[9]     push acc into S[push slot] before the load
-//   hdr[10:14) push slot
-//   hdr[14]    adjoint: the acc operand's subtree contains a constant
-//   hdr[15]    adjoint: the src operand contains a constant
-//   hdr[16:24) src operand: variable index | constant ordinal | pop slot
-//   hdr[24:32) load operand: variable index | constant ordinal
+// The header is laid out for the interpreters' scalar dispatch: every
+// decision they take is a single-bit test (s_bitcmp + branch), and the
+// operand fields need no further decoding.
+//   hdr[0:4)   op (UOP_*)
+//   hdr[4]     CHEAP: op is ADD, SUB, RSUB or MUL
+//   hdr[5]     END
+//   hdr[6]     LDV: load prefix is a variable (acc <- x[var1] before the op)
+//   hdr[7]     LDC: load prefix is a constant (acc <- c); the load prefix is
+//              the first leaf of a subtree
+//   hdr[8]     PUSH: push acc into S[push slot] before the load
+//   hdr[9]     TPRE: the src operand is the uop's first variable (x[var1])
+//   hdr[10]    SC: the src operand is a constant (the payload)
+//   hdr[11]    SP: the src operand pops S[arg2]
+//   hdr[12]    TX2: the src operand is a second variable (x[arg2]; LDV is set)
+//   The uop reads a variable iff LDV or TPRE is set; var1 is the first one.
+//   hdr[13]    adjoint: the acc operand's subtree contains a constant
+//   hdr[14]    adjoint: the src operand contains a constant
+//   hdr[15:18) push slot
+//   hdr[18:24) var1
+//   hdr[24:32) arg2: the constant's ordinal (SC or LDC), the src variable
+//              when both operands are variables, or the popped slot
 // At most one of {src, load} is a constant, so one payload suffices.
 #pragma once
 #include <cstdint>
@@ -54,20 +65,56 @@ enum UopOp : uint32_t {
 enum : uint32_t { SRC_NONE = 0, SRC_VAR = 1, SRC_CONST = 2, SRC_POP = 3 };
 enum : uint32_t { LD_NONE = 0, LD_VAR = 1, LD_CONST = 2 };
 
-constexpr uint32_t HDR_PUSH = 1u << 9;
-constexpr uint32_t HDR_ADJ_ACC = 1u << 14;
-constexpr uint32_t HDR_ADJ_SRC = 1u << 15;
+constexpr uint32_t U_CHEAP = 1u << 4;
+constexpr uint32_t U_END = 1u << 5;
+constexpr uint32_t U_LDV = 1u << 6;
+constexpr uint32_t U_LDC = 1u << 7;
+constexpr uint32_t HDR_PUSH = 1u << 8;
+constexpr uint32_t U_TPRE = 1u << 9;
+constexpr uint32_t U_SC = 1u << 10;
+constexpr uint32_t U_SP = 1u << 11;
+constexpr uint32_t U_TX2 = 1u << 12;
+constexpr uint32_t U_SV = U_TPRE | U_TX2;   // src is a variable
+constexpr uint32_t U_V1 = U_LDV | U_TPRE;   // the uop reads a first variable
+constexpr uint32_t HDR_ADJ_ACC = 1u << 13;
+constexpr uint32_t HDR_ADJ_SRC = 1u << 14;
+constexpr uint32_t UOP_END_HDR = uint32_t(UOP_END) | U_END;
 
-__host__ __device__ constexpr inline uint32_t uop_op(uint32_t h) { return h & 31u; }
-__host__ __device__ constexpr inline uint32_t uop_src(uint32_t h) { return (h >> 5) & 3u; }
-__host__ __device__ constexpr inline uint32_t uop_load(uint32_t h) { return (h >> 7) & 3u; }
-__host__ __device__ constexpr inline uint32_t uop_push_slot(uint32_t h) { return (h >> 10) & 15u; }
-__host__ __device__ constexpr inline uint32_t uop_src_arg(uint32_t h) { return (h >> 16) & 255u; }
-__host__ __device__ constexpr inline uint32_t uop_load_arg(uint32_t h) { return h >> 24; }
+__host__ __device__ constexpr inline uint32_t uop_op(uint32_t h) { return h & 15u; }
+__host__ __device__ constexpr inline uint32_t uop_push_slot(uint32_t h) { return (h >> 15) & 7u; }
+__host__ __device__ constexpr inline uint32_t uop_var1(uint32_t h) { return (h >> 18) & 63u; }
+__host__ __device__ constexpr inline uint32_t uop_arg2(uint32_t h) { return h >> 24; }
+__host__ __device__ constexpr inline uint32_t uop_src(uint32_t h) {
+  return (h & U_SV) ? SRC_VAR : (h & U_SC) ? SRC_CONST : (h & U_SP) ? SRC_POP : SRC_NONE;
+}
+__host__ __device__ constexpr inline uint32_t uop_load(uint32_t h) {
+  return (h & U_LDV) ? LD_VAR : (h & U_LDC) ? LD_CONST : LD_NONE;
+}
+// src operand: variable index, constant ordinal or popped slot
+__host__ __device__ constexpr inline uint32_t uop_src_arg(uint32_t h) {
+  return (h & U_TPRE) ? uop_var1(h) : uop_arg2(h);
+}
+// load operand: variable index or constant ordinal
+__host__ __device__ constexpr inline uint32_t uop_load_arg(uint32_t h) {
+  return (h & U_LDV) ? uop_var1(h) : uop_arg2(h);
+}
 
 __host__ __device__ constexpr inline uint32_t make_hdr(uint32_t op, uint32_t src, uint32_t srcarg,
                                                        uint32_t load, uint32_t loadarg) {
-  return op | (src << 5) | (load << 7) | (srcarg << 16) | (loadarg << 24);
+  const uint32_t flags = (op >= UOP_ADD && op <= UOP_MUL ? U_CHEAP : 0u) |
+                         (op == UOP_END ? U_END : 0u) | (load == LD_VAR ? U_LDV : 0u) |
+                         (load == LD_CONST ? U_LDC : 0u) |
+                         (src == SRC_VAR ? (load == LD_VAR ? U_TX2 : U_TPRE) : 0u) |
+                         (src == SRC_CONST ? U_SC : 0u) | (src == SRC_POP ? U_SP : 0u);
+  const uint32_t var1 = load == LD_VAR ? loadarg : src == SRC_VAR ? srcarg : 0u;
+  const uint32_t arg2 = (src == SRC_CONST || src == SRC_POP) ? srcarg
+                        : load == LD_CONST                   ? loadarg
+                        : (src == SRC_VAR && load == LD_VAR) ? srcarg
+                                                             : 0u;
+  return op | flags | ((var1 & 63u) << 18) | ((arg2 & 255u) << 24);
+}
+__host__ __device__ constexpr inline uint32_t with_push(uint32_t h, uint32_t slot) {
+  return h | HDR_PUSH | ((slot & 7u) << 15);
 }
 
 // Adjoint tape rule: how many per-row factors a uop stores in the forward
