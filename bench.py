@@ -35,7 +35,7 @@ SYM_NAME = {0: "add", 1: "sub", 2: "mul", 3: "div", 4: "sin", 5: "cos", 6: "sq",
 ADJ_SOURCES = ["paper_2605_30954_amd/csrc/k_adjoint.hip", "paper_2605_30954_amd/csrc/interp.h",
                "paper_2605_30954_amd/csrc/devmath.h", "paper_2605_30954_amd/csrc/uop.h",
                "paper_2605_30954_amd/csrc/kernels.h", "paper_2605_30954_amd/build.py"]
-ADJ_KERNELS = ("k_adj_partition", "k_adj_reg", "k_adj_lds")
+ADJ_KERNELS = ("k_adj_partition", "k_adj_path", "k_adj_reg", "k_adj_lds")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_cfg2_traffic.json")
 
 
@@ -136,8 +136,9 @@ def program_work(ops, status, s1, nconst, c):
     status 0, b != 0 and at least one constant, the only ones it evaluates):
     every operator costs c(op); an operator with a constant below it adds its
     local partials c(d op), and each of its children with a constant below
-    adds one product on the reverse sweep (none for + and -, whose partials
-    are +-1)."""
+    adds one product of the chain rule (none for + and -, whose partials are
+    +-1).  This is the work of the gradient itself, whichever order (reverse
+    sweep or path forward mode) the kernels apply the chain rule in."""
     fwd = adj = 0.0
     for m in range(ops.shape[0]):
         if status[m] != 0:
@@ -189,12 +190,12 @@ def roofline(gg, ops, cfg, N, stream, step, steps, fit_aux):
     launches = {k: v[0] / steps for k, v in rep.items()}
     # the adjoint's tier kernels split the individuals between them (after a
     # partition kernel that lists each tier): together they are one launch
-    adj_parts = ("adjoint_partition", "adjoint_reg", "adjoint_reg_b", "adjoint_lds")
+    adj_parts = ("adjoint_partition", "adjoint_path", "adjoint_reg", "adjoint_reg_b", "adjoint_lds")
     adj_ms = sum(per.get(k, 0.0) for k in adj_parts)
     cand = {"fused_forward": per.get("fused_forward", 0.0), "adjoint": adj_ms}
     dom = max(cand, key=cand.get)
     avg_s = cand[dom] * 1e-3 / max(1.0, launches.get("fused_forward" if dom == "fused_forward"
-                                                     else "adjoint_reg", 1.0))
+                                                     else "adjoint_partition", 1.0))
     achieved = alg[dom] / avg_s
     fwd_s = per.get("fused_forward", 0.0) * 1e-3
     traffic = load_traffic() if dom == "adjoint" else None

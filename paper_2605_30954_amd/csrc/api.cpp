@@ -69,8 +69,9 @@ int adj_span_cap(const Shape& s) {
 }
 
 struct Layout {
-  size_t stats, yscr, meta, uops, ab, part, plain_part, ticket, gpart, adjl, tune, total;
+  size_t stats, yscr, meta, uops, merges, ab, part, plain_part, ticket, gpart, adjl, tune, total;
   int U_stride;
+  int MT;  // merge descriptors per program
 };
 
 Layout layout_of(const Shape& s) {
@@ -85,6 +86,9 @@ Layout layout_of(const Shape& s) {
   o = align256(o + size_t(s.M) * sizeof(ProgMeta));
   l.uops = o;
   o = align256(o + size_t(s.M) * l.U_stride * sizeof(uint2));
+  l.MT = std::max(1, s.C_max);
+  l.merges = o;
+  o = align256(o + size_t(s.M) * l.MT * sizeof(uint32_t));
   l.ab = o;
   o = align256(o + size_t(s.M) * 2 * sizeof(double));
   l.part = o;
@@ -121,8 +125,8 @@ TuneKey tune_key(const Shape& s, bool grad) {
 }
 struct Tuned {
   int K, R, G;
-  int TC;  // adjoint tier A tape entries (0 for the forward)
-  int F;   // adjoint: 2 = forward mode for programs with <= 2 constants, 0 = reverse only
+  int TC;  // adjoint: tier A tape entries when F = 0 (0 for the forward)
+  int F;   // adjoint: path tier constants NC (K, R, G are then the path tier's); 0 = no path tier
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuned> g_tuned;  // forward choices
@@ -170,22 +174,34 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   return c;
 }
 
-// Adjoint plan.  Tier A: K rows per lane with a TC-entry register tape,
-// (K, TC) = (4, 16) unless tuned to (2, 16) or (2, 32); W = 4 waves; a
+// Adjoint plan.  Path tier: programs with at most NC constants in path
+// forward mode, (K, NC) = (4, 16) unless tuned to (4, 8), (8, 8), (2, 16) or
+// (2, 32).
+// Tier A: K rows per lane with a TC-entry register tape, (K, TC) = (4, 16)
+// unless tuned (without a path tier) to (2, 16) or (2, 32).  W = 4 waves; a
 // row tile of at most 32 KB untuned, so that several blocks share a CU.
 // Tier B: (2, 32) for the tapes between tier A's and 32 entries.  Tier C: the
 // largest LDS-tape block that fits the worst-case tape (L_max - 1 entries per
-// wave).  All tiers use the same spans.
+// wave).  All tiers use the same spans, set by the path tier (tier A without
+// one); the other tiers' tiles divide the span.
 bool reg_variant(int K, int TC) { return (K == 4 && TC == 16) || (K == 2 && (TC == 16 || TC == 32)); }
+bool path_variant(int K, int NC) {
+  return (K == 4 && (NC == 16 || NC == 8)) || (K == 8 && NC == 8) || (K == 2 && (NC == 32 || NC == 16));
+}
 
 AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   AdjPlan a;
   const int Cm = std::max(1, s.C_max);
   const int cap = lds_limit_bytes() - 64;  // static LDS of the kernels
+  TileCfg& pt = a.path;
   TileCfg& r = a.reg;
-  r.D = D;
-  r.NP = uop_pairs(s.L_max);
-  r.W = 4;
+  pt.D = r.D = D;
+  pt.NP = r.NP = uop_pairs(s.L_max);
+  pt.W = r.W = 4;
+  pt.K = 4;
+  a.nc_p = 16;
+  pt.G = 16;
+  pt.R = 1024;
   r.K = 4;
   a.tc_a = 16;
   a.tc_b = 32;
@@ -193,36 +209,60 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   r.G = 16;
   r.R = 1024;
   if (t) {
-    if (reg_variant(t->K, t->TC)) {
-      r.K = t->K;
-      a.tc_a = t->TC;
+    if (t->F > 0 && path_variant(t->K, t->F)) {
+      pt.K = t->K;
+      a.nc_p = t->F;
+      pt.R = t->R;
+      pt.G = t->G;
+    } else if (t->F == 0) {
+      a.nc_p = 0;
+      if (reg_variant(t->K, t->TC)) {
+        r.K = t->K;
+        a.tc_a = t->TC;
+      }
+      r.R = t->R;
+      r.G = t->G;
     }
-    r.R = t->R;
-    r.G = t->G;
   }
-  const int BRr = 64 * r.K;
+  const bool path = a.nc_p > 0;
+  TileCfg& lead = path ? pt : r;
   const size_t tile_cap = t ? size_t(cap) : size_t(32 * 1024);
-  while (r.R > BRr && (size_t(s.F) * r.R * 4 + size_t(r.R) * 8 > tile_cap ||
-                       adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts, 1) > size_t(cap)))
-    r.R /= 2;
+  auto lead_lds = [&](int R) {
+    return path ? adjoint_path_lds_bytes(s.F, R, lead.G, Cm, lead.W, a.nc_p)
+                : adjoint_reg_lds_bytes(s.F, R, lead.G, Cm, lead.W, a.lane_consts, 1);
+  };
+  while (lead.R > 64 * lead.K &&
+         (size_t(s.F) * lead.R * 4 + size_t(lead.R) * 8 > tile_cap || lead_lds(lead.R) > size_t(cap)))
+    lead.R /= 2;
   const int64_t Nr = (s.N + 255) / 256 * 256;  // a multiple of every tier's batch
-  if (Nr < r.R) r.R = int(Nr);
-  r.R = std::max(256, r.R / 256 * 256);
-  r.G = std::max(1, std::min(r.G, s.M));
-  r.n_groups = (s.M + r.G - 1) / r.G;
+  if (Nr < lead.R) lead.R = int(Nr);
+  lead.R = std::max(256, lead.R / 256 * 256);
+  lead.G = std::max(1, std::min(lead.G, s.M));
+  lead.n_groups = (s.M + lead.G - 1) / lead.G;
   // spans: enough blocks to fill the chip several times over
-  const int64_t tiles = (s.N + r.R - 1) / r.R;
-  int64_t want = (4096 + r.n_groups - 1) / r.n_groups;
+  const int64_t tiles = (s.N + lead.R - 1) / lead.R;
+  int64_t want = (4096 + lead.n_groups - 1) / lead.n_groups;
   want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, int64_t(span_cap)}));
-  r.tiles_per_span = int((tiles + want - 1) / want);
-  a.span_rows = int64_t(r.tiles_per_span) * r.R;
+  lead.tiles_per_span = int((tiles + want - 1) / want);
+  a.span_rows = int64_t(lead.tiles_per_span) * lead.R;
   a.n_spans = int((s.N + a.span_rows - 1) / a.span_rows);
-  r.n_spans = a.n_spans;
+  lead.n_spans = a.n_spans;
+  if (path) {  // tier A: the path tile or a power-of-two fraction of it
+    r.R = pt.R;
+    while (r.R > 64 * r.K && adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts, 1) > size_t(cap))
+      r.R /= 2;
+    r.G = std::max(1, std::min(r.G, s.M));
+    r.n_groups = (s.M + r.G - 1) / r.G;
+    r.n_spans = a.n_spans;
+    r.tiles_per_span = int(a.span_rows / r.R);
+  }
 
   // A program of L tokens has at most L - 1 tape entries (one per tree edge)
-  // and at most C_max constants, so small shapes never reach tier B or C.
+  // and at most C_max constants, so small shapes never reach tiers A, B or C.
   a.tape_cap = std::max(1, s.L_max - 1);
-  a.need_b = a.tape_cap > a.tc_a && a.tc_b > a.tc_a;
+  const bool beyond_path = !path || Cm > a.nc_p;
+  a.need_a = beyond_path;
+  a.need_b = beyond_path && a.tape_cap > a.tc_a && a.tc_b > a.tc_a;
   // tier B: few individuals, each shared by the block's waves; G_b of them
   // per group, a bounded number of group slots per span (blocks loop)
   TileCfg& b = a.reg_b;
@@ -231,12 +271,8 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   b.G = std::max(1, std::min(4, s.M));
   while (b.G > 1 && adjoint_reg_lds_bytes(s.F, b.R, b.G, Cm, b.W, a.lane_consts, b.W) > size_t(cap)) --b.G;
   b.n_groups = std::min((s.M + b.G - 1) / b.G, 32);
-  a.need_wide = a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts;
-
-  // forward mode inside tier A: programs with at most nt_f constants
-  a.nt_f = 2;
-  if (t && t->F == 0) a.nt_f = 0;
-  a.need_f = a.nt_f > 0 && s.C_max > 0;
+  a.need_wide = beyond_path &&
+                (a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts);
 
   // tier C: its tile must divide span_rows (powers of two <= r.R)
   TileCfg& w = a.wide;
@@ -280,6 +316,10 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
 bool adjoint_plan_fits(const Shape& s, const AdjPlan& a) {
   const int cap = lds_limit_bytes() - 64;
   const int Cm = std::max(1, s.C_max);
+  if (a.nc_p > 0 && adjoint_path_lds_bytes(s.F, a.path.R, a.path.G, Cm, a.path.W, a.nc_p) > size_t(cap))
+    return false;
+  if (a.need_a && adjoint_reg_lds_bytes(s.F, a.reg.R, a.reg.G, Cm, a.reg.W, a.lane_consts, 1) > size_t(cap))
+    return false;
   if (a.need_b &&
       adjoint_reg_lds_bytes(s.F, a.reg_b.R, a.reg_b.G, Cm, a.reg_b.W, a.lane_consts, a.reg_b.W) > size_t(cap))
     return false;
@@ -360,6 +400,7 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   double* yscr = reinterpret_cast<double*>(c.ws + l.yscr);
   ProgMeta* meta = reinterpret_cast<ProgMeta*>(c.ws + l.meta);
   uint2* uops = reinterpret_cast<uint2*>(c.ws + l.uops);
+  uint32_t* merges = reinterpret_cast<uint32_t*>(c.ws + l.merges);
   double* ab = reinterpret_cast<double*>(c.ws + l.ab);
   double* part = reinterpret_cast<double*>(c.ws + l.part);
   double* gpart = reinterpret_cast<double*>(c.ws + l.gpart);
@@ -367,7 +408,7 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   const int D = fp64 ? 8 : fc.D;
   GG_TIMED("ystats", launch_ystats(c.y, c.s.N, stats, yscr, c.stream));
   GG_TIMED("compile", launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, D, l.U_stride,
-                                     uops, meta, c.stream));
+                                     uops, meta, merges, l.MT, c.stream));
   GG_TIMED("probe", launch_probe(fp64, fc.K, D, uops, l.U_stride, meta, c.s.M, d, c.stream));
   const bool sse = c.aux != nullptr || !(c.s.flags & GPGOMEA_LINEAR_SCALING);
   if (c.s.flags & GPGOMEA_PLAIN) {
@@ -388,8 +429,13 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
         double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
         const double* abi = ab + 2 * size_t(i);
         const int* ci = pcounts + 4 * size_t(i);
-        GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
-                                                     abi, gi, list0, ci + 0, c.stream));
+        if (one.nc_p > 0)
+          GG_TIMED("plain_adjoint", launch_adjoint_path(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
+                                                        abi, gi, merges + size_t(i) * l.MT, l.MT, list0,
+                                                        ci + 3, c.stream));
+        if (one.need_a)
+          GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
+                                                       stats, abi, gi, list0, ci + 0, c.stream));
         if (one.need_b)
           GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 1, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
                                                        stats, abi, gi, list0, ci + 1, c.stream));
@@ -411,8 +457,12 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     int* counts = lists + 4 * size_t(c.s.M);
     const size_t M = size_t(c.s.M);
     GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, c.stream));
-    GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                               gpart, lists, counts + 0, c.stream));
+    if (ac.nc_p > 0)
+      GG_TIMED("adjoint_path", launch_adjoint_path(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
+                                                   gpart, merges, l.MT, lists + 3 * M, counts + 3, c.stream));
+    if (ac.need_a)
+      GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
+                                                 ab, gpart, lists, counts + 0, c.stream));
     if (ac.need_b)
       GG_TIMED("adjoint_reg_b", launch_adjoint_reg(ac, 1, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
                                                    ab, gpart, lists + M, counts + 1, c.stream));
@@ -449,7 +499,8 @@ int run_call(const Call& c) {
            uintptr_t(c.s.C_max), uintptr_t(c.s.F), uintptr_t(c.s.N), uintptr_t(c.s.ldx),
            uintptr_t(c.s.flags), uintptr_t(fc.K), uintptr_t(fc.R), uintptr_t(fc.G),
            uintptr_t(ac.reg.R), uintptr_t(ac.reg.G), uintptr_t(ac.reg.K), uintptr_t(ac.tc_a),
-           uintptr_t(ac.n_spans), uintptr_t(ac.nt_f)};
+           uintptr_t(ac.n_spans), uintptr_t(ac.nc_p), uintptr_t(ac.path.K), uintptr_t(ac.path.R),
+           uintptr_t(ac.path.G)};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -669,7 +720,7 @@ bool read_tuning(const char* path, int* n_read) {
           json_int(line, "K", &t.K) && json_int(line, "R", &t.R) && json_int(line, "G", &t.G)))
       continue;
     if (!json_int(line, "TC", &t.TC)) t.TC = 0;
-    if (!json_int(line, "TF", &t.F)) t.F = 2;
+    if (!json_int(line, "TF", &t.F)) t.F = 0;
     if (t.K < 1 || t.R < 64 || t.G < 1) continue;
     (fwd ? g_tuned : g_tuned_adj)[k] = t;
     ++n;
@@ -765,20 +816,24 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   if (with_grad) {
     c.with_grad = true;
     c.grad = grad;
-    const int KT_a[3][2] = {{4, 16}, {2, 16}, {2, 32}};
+    // (K, NC) of the path tier, or (K, TC) of tier A without one (F = 0)
+    struct Cand {
+      int K, TC, F;
+    };
+    const Cand cands[8] = {{4, 0, 16}, {4, 0, 8}, {8, 0, 8}, {2, 0, 16},
+                           {2, 0, 32}, {4, 16, 0}, {2, 16, 0}, {2, 32, 0}};
     const int Rs_a[4] = {256, 512, 1024, 2048};
     const int Gs_a[4] = {4, 8, 16, 32};
-    const int Fs_a[2] = {2, 0};
     Tuned best_a{0, 0, 0, 0, 0};
     float best_a_ms = 1e30f;
-    for (const auto& kt : KT_a)
-    for (int fv : Fs_a) {
-      const int k = kt[0];
+    for (const Cand& cd : cands) {
+      if (cd.F > 0 && C_max == 0) continue;
       for (int r : Rs_a) {
         for (int g : Gs_a) {
-          const Tuned t{k, r, g, kt[1], fv};
+          const Tuned t{cd.K, r, g, cd.TC, cd.F};
           const AdjPlan ac = plan_adjoint(st, fc_best.D, &t, adj_span_cap(s));
-          if (ac.reg.R != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
+          const int lead_r = ac.nc_p > 0 ? ac.path.R : ac.reg.R;
+          if (lead_r != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
           const float ms = time_plans(c, fc_best, ac, trials);
           if (ms < 0.0f) {
             const std::string why = last_error();
@@ -794,7 +849,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     if (best_a.K) {
       g_tuned_adj[tune_key(s, true)] = best_a;
       len += std::snprintf(desc + len, sizeof(desc) - size_t(len),
-                           "; fitness+gradient with adjoint K=%d TC=%d F=%d R=%d G=%d (%.3f ms)",
+                           "; fitness+gradient with adjoint K=%d TC=%d NC=%d R=%d G=%d (%.3f ms)",
                            best_a.K, best_a.TC, best_a.F, best_a.R, best_a.G, double(best_a_ms));
     }
   }

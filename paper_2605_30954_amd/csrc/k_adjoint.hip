@@ -55,16 +55,18 @@ struct AdjParams {
   int64_t span_rows;  // rows per span (common to every tier)
   int tape_cap;       // LDS tape entries per wave (tier C)
   int lane_consts;    // CC: constant columns per wave (register tiers)
+  const uint32_t* merges;  // [M][MT] merge ranges (path tier)
+  int MT;
 };
 
 // Tier of an individual: -1 no gradient work (bad program, non-finite, b = 0
-// or no constant), 0 tier A (register tape, or forward mode for at most ntF
-// constants: one tangent per constant, no tape), 1 register tape B, 2 LDS
-// tape.  (Slot 3 of the lists is unused.)
+// or no constant), 3 path forward mode (at most ncP constants), 0 register
+// tape A, 1 register tape B, 2 LDS tape.
 constexpr int kTiers = 4;
-__device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, int CC, int ntF) {
+constexpr int kTierPath = 3;
+__device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, int CC, int ncP) {
   if (pm.status != 0 || s1 == 0.0 || pm.n_const <= 0) return -1;
-  if (pm.n_const <= ntF) return 0;  // forward mode inside the tier A kernel
+  if (pm.n_const <= ncP) return kTierPath;
   if (pm.n_const <= CC && pm.n_tape <= tcA) return 0;
   if (pm.n_const <= CC && pm.n_tape <= tcB) return 1;
   return 2;
@@ -76,14 +78,14 @@ __device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, 
 constexpr int kPartThreads = 1024;
 __global__ __launch_bounds__(kPartThreads) void k_adj_partition(
     const ProgMeta* __restrict__ meta, const double* __restrict__ ab, int M, int tcA, int tcB,
-    int CC, int ntF, int* __restrict__ lists, int* __restrict__ counts) {
+    int CC, int ncP, int* __restrict__ lists, int* __restrict__ counts) {
   __shared__ int sc[kTiers][kPartThreads];
   const int t = threadIdx.x;
   const int chunk = (M + kPartThreads - 1) / kPartThreads;
   const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
   int n[kTiers] = {0, 0, 0, 0};
   for (int i = lo; i < hi; ++i) {
-    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ntF);
+    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ncP);
 #pragma unroll
     for (int q = 0; q < kTiers; ++q) n[q] += k == q;
   }
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(kPartThreads) void k_adj_partition(
 #pragma unroll
   for (int q = 0; q < kTiers; ++q) w[q] = sc[q][t] - n[q];  // exclusive offsets
   for (int i = lo; i < hi; ++i) {
-    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ntF);
+    const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ncP);
 #pragma unroll
     for (int q = 0; q < kTiers; ++q)
       if (k == q) lists[size_t(q) * M + w[q]++] = i;
@@ -417,31 +419,44 @@ __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
   }
 }
 
-// ----------------------------------------------------------- forward mode
-// Tier F: programs with at most NT constants.  Every value carries NT
-// tangents (d value / d c_q for its program's constants q < NT), propagated
-// with the same local partials as the reverse sweep: one interpreter sweep,
-// no tape and no reverse pass.  A subtree without a constant has zero
-// tangents (the uop's adjoint flags say which operands hold constants), so
-// the tangent work is done only on constant paths.
-template <int K, int NT>
-struct Tangents {
-  typename VecT<float, K>::type q[NT];
-};
-
-template <int K, int D, int NT, class Src>
-__device__ inline typename VecT<float, K>::type run_forward_tangent(
-    const Src& prog, const float* __restrict__ xt, int rstride, int lrow, Tangents<K, NT>& ad) {
-  using V = typename VecT<float, K>::type;
-  Slots<V, D> st;
-  Slots<V, D> sd[NT];  // tangents of the pushed values
-  V acc = 0.0f, t = 0.0f, pre = 0.0f;
-  Tangents<K, NT> td;
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    ad.q[q] = 0.0f;
-    td.q[q] = 0.0f;
+// ------------------------------------------------------- path forward mode
+// Forward accumulation for a tree without a tape.  d p / d c_j is the product
+// of the local partials on the path from constant j to the root.  The
+// constants of any subtree are contiguous in postfix order, so every value
+// carries one "pending" factor per row: the product of the partials from the
+// subtree's last merge (a uop whose two operands both hold constants) up to
+// here, and a register array T holds, per constant, the product from the
+// constant up to that merge.  A uop with a constant in one operand only
+// multiplies that operand's pending factor by its partial; a merge folds each
+// operand's pending factor times its partial into T over the operand's
+// constant range (assigning when the operand is a single constant, which has
+// no entry yet) and restarts the pending factor at 1.  At the root,
+// d p / d c_j = pending * T[j] (T is unused with one constant).
+// The ranges of the merges come from the compile step, one descriptor per
+// merge in uop order (lane m of `mt` holds merge m).
+template <int K, int NC>
+__device__ inline void path_flush(RegTape<K, NC>& T, uint32_t lo, uint32_t n,
+                                  const typename VecT<float, K>::type& f) {
+  if (n == 1) {
+    if (lo < uint32_t(NC)) T.put(int(lo), f);
+    GG_BRANCH();
+  } else {
+    const uint32_t hi = min(lo + n, uint32_t(NC));
+#pragma unroll 1
+    for (uint32_t e = lo; e < hi; ++e) T.put(int(e), T.get(int(e)) * f);
+    GG_BRANCH();
   }
+}
+
+template <int K, int D, int NC, class Src>
+__device__ inline typename VecT<float, K>::type run_forward_path(
+    const Src& prog, uint32_t mt, const float* __restrict__ xt, int rstride, int lrow,
+    RegTape<K, NC>& T, typename VecT<float, K>::type& p) {
+  using V = typename VecT<float, K>::type;
+  Slots<V, D> st, ps;  // values and pending factors of the pushed subtrees
+  V acc = 0.0f, t = 0.0f, pre = 0.0f, q = 1.0f;
+  p = 1.0f;
+  int mi = 0;
   const float* __restrict__ xl = xt + lrow;
   uint2 cur = prog.at(0);
   prefetch_operand<float, K>(cur.x, xl, rstride, pre);
@@ -451,104 +466,77 @@ __device__ inline typename VecT<float, K>::type run_forward_tangent(
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
     const float c = f32_of(cur.y);
-    // operands and their tangents (a constant: unit tangent for its own index)
+    // operands and their pending factors (a constant starts at 1)
     if (h & (U_LDV | U_LDC)) {
       if (h & HDR_PUSH) {
         st.put(uop_push_slot(h), acc);
-#pragma unroll
-        for (int q = 0; q < NT; ++q) sd[q].put(uop_push_slot(h), ad.q[q]);
+        ps.put(uop_push_slot(h), p);
         GG_BRANCH();
       }
       if (h & U_LDV) {
         acc = pre;
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = 0.0f;
         GG_BRANCH();
       } else {
         acc = bcast<float, K>(c);
-        const uint32_t k = uop_arg2(h);
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = uint32_t(q) == k ? 1.0f : 0.0f;
+        p = 1.0f;
         GG_BRANCH();
       }
       GG_BRANCH();
     }
     if (h & U_TPRE) {
       t = pre;
-#pragma unroll
-      for (int q = 0; q < NT; ++q) td.q[q] = 0.0f;
       GG_BRANCH();
     } else if (h & U_SC) {
       t = bcast<float, K>(c);
-      const uint32_t k = uop_arg2(h);
-#pragma unroll
-      for (int q = 0; q < NT; ++q) td.q[q] = uint32_t(q) == k ? 1.0f : 0.0f;
+      q = 1.0f;
       GG_BRANCH();
     } else if (h & U_TX2) {
       t = lds_rows<float, K>(xl + uop_arg2(h) * rstride);
-#pragma unroll
-      for (int q = 0; q < NT; ++q) td.q[q] = 0.0f;
       GG_BRANCH();
     } else if (h & U_SP) {
       st.get(uop_arg2(h), t);
-#pragma unroll
-      for (int q = 0; q < NT; ++q) sd[q].get(uop_arg2(h), td.q[q]);
+      ps.get(uop_arg2(h), q);
       GG_BRANCH();
     }
     prefetch_operand<float, K>(nxt.x, xl, rstride, pre);
+    V fa = 1.0f, fs = 1.0f;  // d result / d acc operand, / d src operand
     if (h & U_CHEAP) {  // ADD 1, SUB 2, RSUB 3, MUL 4
-      if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {
-        if (h & 4u) {
-#pragma unroll
-          for (int q = 0; q < NT; ++q) ad.q[q] = t * ad.q[q] + acc * td.q[q];
-          acc = acc * t;
-          GG_BRANCH();
-        } else if (h & 2u) {
-          if (h & 1u) {
-            acc = t - acc;
-#pragma unroll
-            for (int q = 0; q < NT; ++q) ad.q[q] = td.q[q] - ad.q[q];
-            GG_BRANCH();
-          } else {
-            acc = acc - t;
-#pragma unroll
-            for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] - td.q[q];
-            GG_BRANCH();
-          }
-          GG_BRANCH();
-        } else {
-          acc = acc + t;
-#pragma unroll
-          for (int q = 0; q < NT; ++q) ad.q[q] = ad.q[q] + td.q[q];
-          GG_BRANCH();
-        }
+      if (h & 4u) {
+        fa = t;
+        fs = acc;
+        acc = acc * t;
         GG_BRANCH();
-      } else {  // no constant below: value only
-        if (h & 4u) { acc = acc * t; GG_BRANCH(); }
-        else if (h & 2u) {
-          if (h & 1u) { acc = t - acc; GG_BRANCH(); }
-          else { acc = acc - t; GG_BRANCH(); }
-          GG_BRANCH();
-        } else { acc = acc + t; GG_BRANCH(); }
+      } else if (h & 2u) {
+        if (h & 1u) { fa = -1.0f; acc = t - acc; GG_BRANCH(); }
+        else { fs = -1.0f; acc = acc - t; GG_BRANCH(); }
+        GG_BRANCH();
+      } else {
+        acc = acc + t;
         GG_BRANCH();
       }
       GG_BRANCH();
-    } else if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {  // value, local partials, tangents
-      V fa = 1.0f, fs = 0.0f;
+    } else if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {
       op_partials<K>(uop_op(h), acc, t, fa, fs);
-      // a unary operator has no src operand: fs stays 0 and td is not used
-      if (h & (U_TPRE | U_SC | U_TX2 | U_SP)) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q] + fs * td.q[q];
-        GG_BRANCH();
-      } else {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) ad.q[q] = fa * ad.q[q];
-        GG_BRANCH();
-      }
       GG_BRANCH();
     } else {
       op_value<float, K>(uop_op(h), acc, t);
+      GG_BRANCH();
+    }
+    if (h & HDR_ADJ_ACC) {
+      if (h & HDR_ADJ_SRC) {  // merge
+        const uint32_t md = uint32_t(__builtin_amdgcn_readlane(int(mt), mi));
+        ++mi;
+        path_flush<K, NC>(T, md & 255u, (md >> 8) & 255u, fa * p);
+        path_flush<K, NC>(T, (md >> 16) & 255u, md >> 24, fs * q);
+        p = 1.0f;
+        GG_BRANCH();
+      } else {
+        p = fa * p;
+        GG_BRANCH();
+      }
+      GG_BRANCH();
+    } else if (h & HDR_ADJ_SRC) {
+      p = fs * q;
       GG_BRANCH();
     }
     cur = nxt;
@@ -639,10 +627,7 @@ __device__ inline void reduce_columns(const float* lacc, int nc, int lane, doubl
 // queue.  SPLIT = true (tier B, few individuals): all W waves share each
 // individual, wave w taking batches w, w+W, ... with its own copy of the
 // accumulators, summed in wave order at the end (bitwise repeatable).
-// NT > 0: an individual with at most NT constants is differentiated in
-// forward mode (one sweep, tangents instead of a tape); the others in reverse
-// mode.  One launch serves both kinds, so the queue balances them.
-template <int K, int D, int W, int TC, int NP, bool SPLIT, int NT>
+template <int K, int D, int W, int TC, int NP, bool SPLIT>
 __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int COPIES = SPLIT ? W : 1;
@@ -695,30 +680,13 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
         const double s1 = p.ab[size_t(i) * 2 + 1];
         const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
-        if (NT > 0 && nc <= NT) {  // forward mode (wave-uniform)
-          for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
-            const int lrow = b * BR + lane * K;
-            Tangents<K, (NT > 0 ? NT : 1)> ad;
-            const auto v = run_forward_tangent<K, D, (NT > 0 ? NT : 1)>(prog, xs, R, lrow, ad);
-            const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-            const int kv = max(0, min(K, nvalid - lrow));
-#pragma unroll
-            for (int q = 0; q < (NT > 0 ? NT : 1); ++q) {
-              if (q < nc) {  // wave-uniform
-                const typename VecT<float, K>::type gq = g * ad.q[q];
-                sink.template add<typename VecT<float, K>::type, K>(uint32_t(q), gq, kv);
-              }
-            }
-          }
-        } else {
-          for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
-            const int lrow = b * BR + lane * K;
-            RegTape<K, TC> tape;
-            const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
-            const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-            const int kv = max(0, min(K, nvalid - lrow));
-            run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
-          }
+        for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
+          const int lrow = b * BR + lane * K;
+          RegTape<K, TC> tape;
+          const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
+          const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
+          const int kv = max(0, min(K, nvalid - lrow));
+          run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
         }
         reduce_columns<W>(lacc, nc, lane, gmine + size_t(jj) * p.C_max);
         prog = prog_next;
@@ -733,6 +701,94 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
       }
     }
     adj_write(p, it.span, base, Gn, gacc);  // each thread reads what it summed
+  }
+}
+
+// Path tier: programs with at most NC constants, differentiated in path
+// forward mode (one sweep, no tape).  Waves claim whole individuals from the
+// tile's queue; each lane sums its rows' constant adjoints in an LDS column.
+template <int K, int D, int W, int NC, int NP>
+__global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int R = p.R;
+  float* xs = reinterpret_cast<float*>(smem_raw);
+  double* yts = reinterpret_cast<double*>(smem_raw + size_t(p.F) * R * sizeof(float));
+  double* gacc = yts + R;  // G * C_max
+  float* lacc_all = reinterpret_cast<float*>(gacc + size_t(p.G) * p.C_max);  // W * NC * 65
+
+  const AdjItem it = adj_item(p);
+  const int cnt = __builtin_amdgcn_readfirstlane(*p.count);
+  if (it.slot * p.G >= cnt) return;  // whole block: nothing of this tier here
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const double ybar = p.stats[ST_YBAR];
+  constexpr int BR = 64 * K;
+  float* lacc = lacc_all + size_t(wv) * NC * kColStride;
+  LaneSink sink{lacc + lane};
+  const int GC = p.G * p.C_max;
+  const int64_t s_begin = int64_t(it.span) * p.span_rows;
+  const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
+
+  __shared__ int queue;
+  for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {  // block-uniform
+    const int base = grp * p.G;
+    const int Gn = min(p.G, cnt - base);
+    __syncthreads();  // previous group's partials written
+    for (int j = threadIdx.x; j < GC; j += blockDim.x) gacc[j] = 0.0;
+    for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
+      const int nvalid = int(min<int64_t>(R, s_end - r0));
+      __syncthreads();
+      if (threadIdx.x == 0) queue = 0;
+      adj_stage<W>(p, xs, yts, r0, nvalid, ybar);
+      __syncthreads();
+      const int nbatch = (nvalid + BR - 1) / BR;
+      // the next claimed individual has its program and merge ranges loaded
+      // into registers while this one runs
+      UopRegs<NP> prog, prog_next;
+      uint32_t mt = 0, mt_next = 0;
+      int jj = claim_next(&queue);
+      if (jj < Gn) {
+        const int i0 = p.list[base + jj];
+        prog.load(p.uops + size_t(i0) * p.U_stride, p.U_stride);
+        mt = lane < p.MT ? p.merges[size_t(i0) * p.MT + lane] : 0u;
+      }
+      while (jj < Gn) {  // wave-uniform
+        const int i = __builtin_amdgcn_readfirstlane(p.list[base + jj]);
+        const int jn = claim_next(&queue);
+        if (jn < Gn) {
+          const int i1 = p.list[base + jn];
+          prog_next.load(p.uops + size_t(i1) * p.U_stride, p.U_stride);
+          mt_next = lane < p.MT ? p.merges[size_t(i1) * p.MT + lane] : 0u;
+        }
+        const int nc = __builtin_amdgcn_readfirstlane(p.meta[i].n_const);
+        const double s1 = p.ab[size_t(i) * 2 + 1];
+        const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
+        for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
+        for (int b = 0; b < nbatch; ++b) {
+          const int lrow = b * BR + lane * K;
+          RegTape<K, NC> T;
+          typename VecT<float, K>::type pf;
+          const auto v = run_forward_path<K, D, NC>(prog, mt, xs, R, lrow, T, pf);
+          const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid) * pf;
+          const int kv = max(0, min(K, nvalid - lrow));
+          if (nc == 1) {
+            sink.template add<typename VecT<float, K>::type, K>(0u, g, kv);
+          } else {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              if (j >= nc) break;  // wave-uniform
+              sink.template add<typename VecT<float, K>::type, K>(uint32_t(j), g * T.get(j), kv);
+            }
+          }
+        }
+        reduce_columns<W>(lacc, nc, lane, gacc + size_t(jj) * p.C_max);
+        prog = prog_next;
+        mt = mt_next;
+        jj = jn;
+      }
+    }
+    __syncthreads();
+    adj_write(p, it.span, base, Gn, gacc);
   }
 }
 
@@ -801,34 +857,54 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
 }
 
 template <int K, int D, int W, int TC, int NP>
-static hipError_t reg_impl1(const TileCfg& c, int CC, bool split, int nt, const AdjParams& ap,
+static hipError_t reg_impl1(const TileCfg& c, int CC, bool split, const AdjParams& ap,
                             hipStream_t s) {
   const size_t sh = adjoint_reg_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, CC, split ? W : 1);
   const dim3 grid(ap.n_spans * ap.n_groups), block(W * 64);
   if (split)
-    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, true, 0>), grid, block, sh, s, ap);
-  else if (nt == 2)
-    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false, 2>), grid, block, sh, s, ap);
-  else if (nt == 0)
-    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false, 0>), grid, block, sh, s, ap);
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, true>), grid, block, sh, s, ap);
   else
-    return hipErrorInvalidValue;  // no kernel instantiated for this tangent count
+    hipLaunchKernelGGL((k_adj_reg<K, D, W, TC, NP, false>), grid, block, sh, s, ap);
   return hipGetLastError();
 }
 
 // programs of up to 63 tokens use D = 4 (one register pair); longer ones D = 8
 template <int K, int D, int W, int TC>
-static hipError_t reg_impl(const TileCfg& c, int CC, bool split, int nt, const AdjParams& ap,
+static hipError_t reg_impl(const TileCfg& c, int CC, bool split, const AdjParams& ap,
                            hipStream_t s) {
   if constexpr (D == 4) {
     if (c.NP != 1) return hipErrorInvalidValue;
-    return reg_impl1<K, 4, W, TC, 1>(c, CC, split, nt, ap, s);
+    return reg_impl1<K, 4, W, TC, 1>(c, CC, split, ap, s);
   } else {
     switch (c.NP) {
-      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, split, nt, ap, s);
-      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, split, nt, ap, s);
-      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, split, nt, ap, s);
-      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, split, nt, ap, s);
+      case 1: return reg_impl1<K, 8, W, TC, 1>(c, CC, split, ap, s);
+      case 2: return reg_impl1<K, 8, W, TC, 2>(c, CC, split, ap, s);
+      case 4: return reg_impl1<K, 8, W, TC, 4>(c, CC, split, ap, s);
+      case 8: return reg_impl1<K, 8, W, TC, 8>(c, CC, split, ap, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+}
+
+template <int K, int D, int W, int NC, int NP>
+static hipError_t path_impl1(const TileCfg& c, const AdjParams& ap, hipStream_t s) {
+  const size_t sh = adjoint_path_lds_bytes(ap.F, c.R, c.G, ap.C_max, W, NC);
+  hipLaunchKernelGGL((k_adj_path<K, D, W, NC, NP>), dim3(ap.n_spans * ap.n_groups), dim3(W * 64),
+                     sh, s, ap);
+  return hipGetLastError();
+}
+
+template <int K, int D, int W, int NC>
+static hipError_t path_impl(const TileCfg& c, const AdjParams& ap, hipStream_t s) {
+  if constexpr (D == 4) {
+    if (c.NP != 1) return hipErrorInvalidValue;
+    return path_impl1<K, 4, W, NC, 1>(c, ap, s);
+  } else {
+    switch (c.NP) {
+      case 1: return path_impl1<K, 8, W, NC, 1>(c, ap, s);
+      case 2: return path_impl1<K, 8, W, NC, 2>(c, ap, s);
+      case 4: return path_impl1<K, 8, W, NC, 4>(c, ap, s);
+      case 8: return path_impl1<K, 8, W, NC, 8>(c, ap, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -844,16 +920,17 @@ static hipError_t lds_impl(const TileCfg& c, const AdjParams& ap, hipStream_t s)
 static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, const uint2* uops,
                             int U_stride, const ProgMeta* meta, int M, int C_max,
                             const DataArgs& d, const double* stats, const double* ab,
-                            double* gpart, const int* list, const int* count) {
+                            double* gpart, const int* list, const int* count,
+                            const uint32_t* merges = nullptr, int MT = 0) {
   return AdjParams{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
                    list, count, c.R, c.G, n_groups, a.n_spans, a.span_rows, a.tape_cap,
-                   a.lane_consts};
+                   a.lane_consts, merges, MT};
 }
 
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                     int* lists, int* counts, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_partition, dim3(1), dim3(kPartThreads), 0, s, meta, ab, M, a.tc_a,
-                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.need_f ? a.nt_f : 0, lists, counts);
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.nc_p, lists, counts);
   return hipGetLastError();
 }
 
@@ -861,13 +938,13 @@ hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, cons
 // else 0, and list0[0] = 0 (each per-individual launch lists its one individual).
 __global__ __launch_bounds__(256) void k_adj_tier_flags(const ProgMeta* __restrict__ meta,
                                                         const double* __restrict__ ab, int M,
-                                                        int tcA, int tcB, int CC, int ntF,
+                                                        int tcA, int tcB, int CC, int ncP,
                                                         int* __restrict__ counts,
                                                         int* __restrict__ list0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) list0[0] = 0;
   if (i >= M) return;
-  const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ntF);
+  const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ncP);
 #pragma unroll
   for (int q = 0; q < kTiers; ++q) counts[kTiers * i + q] = k == q;
 }
@@ -875,7 +952,7 @@ __global__ __launch_bounds__(256) void k_adj_tier_flags(const ProgMeta* __restri
 hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                      int* counts, int* list0, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_tier_flags, dim3((M + 255) / 256), dim3(256), 0, s, meta, ab, M, a.tc_a,
-                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.need_f ? a.nt_f : 0, counts, list0);
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.nc_p, counts, list0);
   return hipGetLastError();
 }
 
@@ -889,14 +966,35 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
                                   gpart, list, count);
   const int CC = a.lane_consts;
   const bool split = tier == 1;  // tier B: few individuals, the waves share each one
-  const int nt = tier == 0 && a.need_f ? a.nt_f : 0;  // forward mode in tier A
   if (c.W != 4) return hipErrorInvalidValue;
-  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, split, nt, ap, s);
-  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, split, nt, ap, s);
-  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, split, nt, ap, s);
-  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, split, nt, ap, s);
-  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, split, nt, ap, s);
-  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, split, nt, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 4) return reg_impl<4, 4, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 4 && TC == 16 && c.D == 8) return reg_impl<4, 8, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 4) return reg_impl<2, 4, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 16 && c.D == 8) return reg_impl<2, 8, 4, 16>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 4) return reg_impl<2, 4, 4, 32>(c, CC, split, ap, s);
+  if (c.K == 2 && TC == 32 && c.D == 8) return reg_impl<2, 8, 4, 32>(c, CC, split, ap, s);
+  return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
+}
+
+hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
+                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                               const double* stats, const double* ab, double* gpart,
+                               const uint32_t* merges, int MT, const int* list, const int* count,
+                               hipStream_t s) {
+  const TileCfg& c = a.path;
+  const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
+                                  gpart, list, count, merges, MT);
+  if (c.W != 4 || MT < 1) return hipErrorInvalidValue;
+  if (c.K == 4 && a.nc_p == 16 && c.D == 4) return path_impl<4, 4, 4, 16>(c, ap, s);
+  if (c.K == 4 && a.nc_p == 16 && c.D == 8) return path_impl<4, 8, 4, 16>(c, ap, s);
+  if (c.K == 8 && a.nc_p == 8 && c.D == 4) return path_impl<8, 4, 4, 8>(c, ap, s);
+  if (c.K == 8 && a.nc_p == 8 && c.D == 8) return path_impl<8, 8, 4, 8>(c, ap, s);
+  if (c.K == 2 && a.nc_p == 32 && c.D == 4) return path_impl<2, 4, 4, 32>(c, ap, s);
+  if (c.K == 2 && a.nc_p == 32 && c.D == 8) return path_impl<2, 8, 4, 32>(c, ap, s);
+  if (c.K == 4 && a.nc_p == 8 && c.D == 4) return path_impl<4, 4, 4, 8>(c, ap, s);
+  if (c.K == 4 && a.nc_p == 8 && c.D == 8) return path_impl<4, 8, 4, 8>(c, ap, s);
+  if (c.K == 2 && a.nc_p == 16 && c.D == 4) return path_impl<2, 4, 4, 16>(c, ap, s);
+  if (c.K == 2 && a.nc_p == 16 && c.D == 8) return path_impl<2, 8, 4, 16>(c, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape
 }
 

@@ -96,6 +96,7 @@ constexpr int kLMax = 512;
 
 struct CompileLds {
   int16_t kl[kLMax], kr[kLMax], ci[kLMax], stk[kLMax];
+  int16_t clo[kLMax], cnum[kLMax];  // constants of the subtree: ordinals [clo, clo + cnum)
   int8_t sym[kLMax];
   uint8_t need[kLMax], hasc[kLMax], stt[kLMax];
 };
@@ -143,6 +144,8 @@ __device__ inline int uop_cost(uint32_t op) {
 struct Emitter {
   uint2* out;
   const float* cs;
+  uint32_t* merges;  // one descriptor per merge, in uop order
+  int merge_cap = 0, n_merge = 0;
   int n = 0, cap = 0, tape = 0, cost = 0;
   bool push_pending = false;
   uint32_t push_slot = 0;
@@ -161,6 +164,15 @@ struct Emitter {
     out[n++] = make_uint2(hdr, payload);
     tape += tape_acc(hdr) + tape_src(hdr);
     cost += uop_cost(uop_op(hdr));
+  }
+  // the uop just emitted merges two operands that both hold constants: their
+  // constant ordinal ranges (each operand's constants are contiguous in
+  // postfix order)
+  __device__ inline void merge(int loA, int nA, int loS, int nS) {
+    if (n_merge < merge_cap)
+      merges[n_merge] = uint32_t(loA) | (uint32_t(nA) << 8) | (uint32_t(loS) << 16) |
+                        (uint32_t(nS) << 24);
+    ++n_merge;
   }
 };
 
@@ -184,7 +196,8 @@ __device__ inline void term_operand(const CompileLds& L, int t, const float* cs,
 __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops, int M, int L_max,
                                                  const float* __restrict__ consts, int C_max, int F,
                                                  int Dmax, int U_stride, uint2* __restrict__ uops,
-                                                 ProgMeta* __restrict__ meta) {
+                                                 ProgMeta* __restrict__ meta,
+                                                 uint32_t* __restrict__ merges, int MT) {
   __shared__ CompileLds smem[4];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + w;
@@ -208,11 +221,14 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
     const int ar = arity_of(s);
     L.kl[t] = L.kr[t] = -1;
     L.ci[t] = -1;
+    L.clo[t] = int16_t(nc);
+    L.cnum[t] = 0;
     if (ar == 0) {
       if (s == GPGOMEA_SYM_CONST) {
         if (nc >= C_max) bad = true;
         L.ci[t] = int16_t(nc++);
         L.hasc[t] = 1;
+        L.cnum[t] = 1;
       } else if (s >= GPGOMEA_SYM_VAR0 && s - GPGOMEA_SYM_VAR0 < F) {
         L.hasc[t] = 0;
       } else {
@@ -239,11 +255,15 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
         }
         L.need[t] = uint8_t(nd > 255 ? 255 : nd);
         L.hasc[t] = L.hasc[a] | L.hasc[b];
+        L.clo[t] = L.clo[a];  // the left operand's constants come first in postfix
+        L.cnum[t] = int16_t(L.cnum[a] + L.cnum[b]);
       } else {
         const int a = L.stk[--sp];
         L.kl[t] = int16_t(a);
         L.need[t] = L.need[a];
         L.hasc[t] = L.hasc[a];
+        L.clo[t] = L.clo[a];
+        L.cnum[t] = L.cnum[a];
       }
     }
     L.stk[sp++] = int16_t(t);
@@ -252,6 +272,8 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
   Emitter E;
   E.out = out;
   E.cs = cs;
+  E.merges = merges + size_t(i) * MT;
+  E.merge_cap = MT;
   E.cap = U_stride - 2;
   int maxsp = 0;
   if (!bad) {
@@ -307,6 +329,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
         if (ka == SRC_CONST && kb == SRC_CONST) {
           E.emit(make_hdr(UOP_NOP, SRC_NONE, 0, LD_CONST, aa) | HDR_ADJ_ACC, pa);
           E.emit(make_hdr(bin_uop(s, false), SRC_CONST, ab, LD_NONE, 0) | HDR_ADJ_ACC | HDR_ADJ_SRC, pb);
+          E.merge(L.ci[a], 1, L.ci[b], 1);
         } else if (ka == SRC_CONST) {  // load the variable b, constant a is the src: a op b
           E.emit(make_hdr(bin_uop(s, true), SRC_CONST, aa, LD_VAR, ab) | HDR_ADJ_SRC, pa);
         } else {  // load variable a; b is a variable or a constant
@@ -331,6 +354,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
         E.emit(make_hdr(bin_uop(s, ta), k, ar2, LD_NONE, 0) | (L.hasc[nt] ? HDR_ADJ_ACC : 0) |
                    (hc ? HDR_ADJ_SRC : 0),
                pay);
+        if (L.hasc[nt] && hc) E.merge(L.clo[nt], L.cnum[nt], L.ci[tt], 1);
         --top;
         continue;
       }
@@ -361,6 +385,8 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
       E.emit(make_hdr(bin_uop(s, !b_first), SRC_POP, uint32_t(dsp), LD_NONE, 0) |
                  (L.hasc[second] ? HDR_ADJ_ACC : 0) | (L.hasc[first] ? HDR_ADJ_SRC : 0),
              0);
+      if (L.hasc[second] && L.hasc[first])
+        E.merge(L.clo[second], L.cnum[second], L.clo[first], L.cnum[first]);
       --top;
     }
   }
@@ -378,6 +404,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
     pm.n_tape = E.tape;
     pm.n_const = nc;
     pm.cost = E.cost;
+    pm.n_merge = E.n_merge;
   }
   pm.mu = 0.0f;
   meta[i] = pm;
@@ -385,10 +412,10 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
 
 hipError_t launch_compile(const int8_t* ops, int M, int L_max, const float* consts, int C_max,
                           int F, int Dmax, int U_stride, uint2* uops, ProgMeta* meta,
-                          hipStream_t s) {
+                          uint32_t* merges, int MT, hipStream_t s) {
   const int nb = (M + 3) / 4;
   hipLaunchKernelGGL(k_compile, dim3(nb), dim3(256), 0, s, ops, M, L_max, consts, C_max, F, Dmax,
-                     U_stride, uops, meta);
+                     U_stride, uops, meta, merges, MT);
   return hipGetLastError();
 }
 

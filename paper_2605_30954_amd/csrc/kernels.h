@@ -43,8 +43,11 @@ struct DataArgs {
 
 hipError_t launch_ystats(const float* y, int64_t N, double* stats, double* scratch, hipStream_t s);
 
+// merges[i][m] (m < MT): constant ranges of the two operands of the m-th uop of
+// program i whose operands both hold constants (loA | nA<<8 | loS<<16 | nS<<24)
 hipError_t launch_compile(const int8_t* ops, int M, int L_max, const float* consts, int C_max,
-                          int F, int Dmax, int U_stride, uint2* uops, ProgMeta* meta, hipStream_t s);
+                          int F, int Dmax, int U_stride, uint2* uops, ProgMeta* meta,
+                          uint32_t* merges, int MT, hipStream_t s);
 
 // mean prediction over the first rows -> meta[i].mu
 hipError_t launch_probe(bool fp64, int K, int D, const uint2* uops, int U_stride, ProgMeta* meta,
@@ -73,7 +76,7 @@ int plain_blocks(const TileCfg& c, int64_t N);
 // rows into the same n_spans spans of span_rows rows.  A tier's n_groups is
 // the number of group slots its grid holds per span.
 struct AdjPlan {
-  TileCfg reg, reg_b, wide;
+  TileCfg path, reg, reg_b, wide;
   int n_spans = 1;
   int64_t span_rows = 0;
   int tc_a = 16, tc_b = 32;  // register tape entries of tiers A and B
@@ -81,11 +84,12 @@ struct AdjPlan {
   int tape_cap = 1;          // LDS tape entries per wave of tier C
   bool need_b = true;        // some program of this shape may fall in tier B
   bool need_wide = true;     // ... in tier C
-  int nt_f = 2;              // tier A differentiates programs with <= nt_f constants
-  bool need_f = true;        // in forward mode (nt_f tangents per value)
+  int nc_p = 16;             // path tier: programs with <= nc_p constants (0: none)
+  bool need_a = true;        // some program of this shape may fall in tier A
 };
 
-// Tier lists: lists[tier * M + k], counts[tier], tier = 0 A, 1 B, 2 C (after finalize).
+// Tier lists: lists[tier * M + k], counts[tier], tier = 0 A, 1 B, 2 C, 3 path
+// (after finalize).
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                     int* lists, int* counts, hipStream_t s);
 // Plain form: counts[4i + tier] = 1 for individual i's tier, list0[0] = 0.
@@ -96,6 +100,11 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
                               const int* list, const int* count, hipStream_t s);
+hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
+                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
+                               const double* stats, const double* ab, double* gpart,
+                               const uint32_t* merges, int MT, const int* list, const int* count,
+                               hipStream_t s);
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
@@ -123,6 +132,11 @@ inline size_t adjoint_lds_bytes(int F, int R, int G, int C_max, int W, int K, in
 inline size_t adjoint_reg_lds_bytes(int F, int R, int G, int C_max, int W, int CC, int copies) {
   return size_t(F) * R * 4 + size_t(R) * 8 + size_t(copies) * G * C_max * 8 +
          size_t(W) * CC * 65 * 4;
+}
+// LDS bytes of one path-tier block (row tile, centred targets, constant
+// accumulators, W waves x NC per-lane constant columns of 65 floats).
+inline size_t adjoint_path_lds_bytes(int F, int R, int G, int C_max, int W, int NC) {
+  return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * C_max * 8 + size_t(W) * NC * 65 * 4;
 }
 inline size_t forward_lds_bytes(int F, int R, int G) {
   return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * 4 * 8 + 16;

@@ -153,7 +153,7 @@ struct ProgMeta {
   int32_t n_const;  // constants used
   int32_t cost;     // estimated VALU work per row (planning)
   float mu;         // shift for the moment sums (mean prediction on the first rows)
-  int32_t pad;
+  int32_t n_merge;  // uops whose two operands both hold constants
 };
 
 }  // namespace gg

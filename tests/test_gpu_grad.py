@@ -112,3 +112,42 @@ def test_autograd_function():
     want = (w[:, None] * grad).float()
     assert torch.allclose(c.grad[ok], want[ok], rtol=1e-6, atol=0)
     assert torch.equal(f, fit)
+
+
+def _tune_entry(path, cfg, M, N, K, R, G, TC, NC):
+    """A one-entry tuning file forcing the adjoint plan of this exact shape."""
+    lcls = int(np.floor(np.log2(cfg.L_max + 1)))
+    ncls, mcls = int(np.floor(np.log2(N))), int(np.floor(np.log2(M)))
+    with open(path, "w") as fh:
+        fh.write('{"entries": [\n  {"table": "adj", "fp64": 0, "Lcls": %d, "F": %d, "Ncls": %d, '
+                 '"Mcls": %d, "grad": 1, "K": %d, "R": %d, "G": %d, "TC": %d, "TF": %d}\n]}\n'
+                 % (lcls, cfg.F, ncls, mcls, K, R, G, TC, NC))
+
+
+@pytest.mark.parametrize("cid,M,N", [(4, 40, 5000), (5, 48, 2500)])
+def test_gradient_every_tier_variant(cid, M, N, tmp_path):
+    """Each path-tier variant (K, NC) and the tape tiers alone (no path tier)
+    against the oracle on the same batch; height-5 programs run the D = 4
+    kernels, height 7 the D = 8 ones with programs held in four register
+    pairs.  (The shapes are used by no other test: a loaded plan stays in
+    force for its shape class.)"""
+    cfg = get_config(cid)
+    d = make_inputs(cfg, M, N, salt=11)
+    ops, cs, X, y = to_device(d)
+    idx = list(range(M))
+    vy = float(np.var(d["y"].astype(np.float64)))
+    fl = oracle_flags(d, idx, "f32", True, with_grad=True)
+    refs = oracle_gradients(d, idx, True)
+    nc = d["nc"]
+    log(f"[case] tier variants cfg{cid} M={M} N={N} constants per program {np.bincount(nc).tolist()}")
+    gated = []
+    for K, TC, NC in [(4, 0, 16), (4, 0, 8), (8, 0, 8), (2, 0, 16), (2, 0, 32), (4, 16, 0), (2, 32, 0)]:
+        path = str(tmp_path / f"tune_{K}_{TC}_{NC}.json")
+        _tune_entry(path, cfg, M, N, K, 512, 8, TC, NC)
+        assert gg.load_tuning(path) == 1
+        log(f"[variant] K={K} TC={TC} NC={NC}")
+        fit, grad, st = gg.grad_consts(ops, cs, X, y, return_status=True)
+        grad, st = grad.cpu().numpy(), st.cpu().numpy()
+        rep = gate_gradients(grad, st, refs, fl, vy, what=f"cfg{cid} K={K} TC={TC} NC={NC}")
+        gated.append(rep["gated"])
+    assert min(gated) >= 6
