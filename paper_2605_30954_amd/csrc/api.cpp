@@ -99,7 +99,8 @@ Layout layout_of(const Shape& s) {
   o = align256(o + 64);
   l.gpart = o;
   o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
-  l.adjl = o;  // adjoint tier lists [4][M] + counts [4], or per-individual counts [M][4] + a list
+  l.adjl = o;  // adjoint tier lists [4][M] + counts [4] + path redo flags [M] at 5M, or
+               // per-individual counts [M][4] + a list
   o = align256(o + size_t(s.M) * 8 * sizeof(int32_t) + 64);
   l.tune = o;  // outputs of the autotuner's trial calls: fitness, grad, status
   o = align256(o + size_t(s.M) * (std::max(s.C_max, 1) + 2) * sizeof(double));
@@ -175,8 +176,8 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
 }
 
 // Adjoint plan.  Path tier: programs with at most NC constants in path
-// forward mode, (K, NC) = (4, 16) unless tuned to (4, 8), (8, 8), (2, 16) or
-// (2, 32).
+// forward mode, (K, NC) = (4, 16) unless tuned to (4, 12), (4, 8), (8, 8),
+// (2, 16) or (2, 32).
 // Tier A: K rows per lane with a TC-entry register tape, (K, TC) = (4, 16)
 // unless tuned (without a path tier) to (2, 16) or (2, 32).  W = 4 waves; a
 // row tile of at most 32 KB untuned, so that several blocks share a CU.
@@ -186,7 +187,8 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
 // one); the other tiers' tiles divide the span.
 bool reg_variant(int K, int TC) { return (K == 4 && TC == 16) || (K == 2 && (TC == 16 || TC == 32)); }
 bool path_variant(int K, int NC) {
-  return (K == 4 && (NC == 16 || NC == 8)) || (K == 8 && NC == 8) || (K == 2 && (NC == 32 || NC == 16));
+  return (K == 4 && (NC == 16 || NC == 12 || NC == 8)) || (K == 8 && NC == 8) ||
+         (K == 2 && (NC == 32 || NC == 16));
 }
 
 AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
@@ -260,9 +262,11 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   // A program of L tokens has at most L - 1 tape entries (one per tree edge)
   // and at most C_max constants, so small shapes never reach tiers A, B or C.
   a.tape_cap = std::max(1, s.L_max - 1);
+  // with a path tier, individuals whose partials overflow fall back to tier B
+  // (or C for tapes longer than tier B's)
   const bool beyond_path = !path || Cm > a.nc_p;
   a.need_a = beyond_path;
-  a.need_b = beyond_path && a.tape_cap > a.tc_a && a.tc_b > a.tc_a;
+  a.need_b = (beyond_path && a.tape_cap > a.tc_a && a.tc_b > a.tc_a) || path;
   // tier B: few individuals, each shared by the block's waves; G_b of them
   // per group, a bounded number of group slots per span (blocks loop)
   TileCfg& b = a.reg_b;
@@ -271,8 +275,9 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   b.G = std::max(1, std::min(4, s.M));
   while (b.G > 1 && adjoint_reg_lds_bytes(s.F, b.R, b.G, Cm, b.W, a.lane_consts, b.W) > size_t(cap)) --b.G;
   b.n_groups = std::min((s.M + b.G - 1) / b.G, 32);
-  a.need_wide = beyond_path &&
-                (a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts);
+  a.need_wide = (beyond_path &&
+                 (a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts)) ||
+                (path && a.tape_cap > a.tc_b);
 
   // tier C: its tile must divide span_rows (powers of two <= r.R)
   TileCfg& w = a.wide;
@@ -419,8 +424,10 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
       GG_TIMED("plain_forward", launch_plain_forward(fp64, fc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
                                                      c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
     if (c.with_grad) {
+      // the plain form differentiates with the tape tiers only
+      const Tuned tape_only{4, 1024, 16, 16, 0};
       const AdjPlan one = plan_adjoint(Shape{1, c.s.L_max, c.s.C_max, c.s.F, c.s.N, c.s.ldx, c.s.flags}, D,
-                                       nullptr, adj_span_cap(c.s));
+                                       &tape_only, adj_span_cap(c.s));
       int* pcounts = reinterpret_cast<int*>(c.ws + l.adjl);
       int* list0 = pcounts + 4 * size_t(c.s.M);
       GG_TIMED("plain_tiers", launch_adjoint_tier_flags(one, meta, ab, c.s.M, pcounts, list0, c.stream));
@@ -429,10 +436,6 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
         double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
         const double* abi = ab + 2 * size_t(i);
         const int* ci = pcounts + 4 * size_t(i);
-        if (one.nc_p > 0)
-          GG_TIMED("plain_adjoint", launch_adjoint_path(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
-                                                        abi, gi, merges + size_t(i) * l.MT, l.MT, list0,
-                                                        ci + 3, c.stream));
         if (one.need_a)
           GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
                                                        stats, abi, gi, list0, ci + 0, c.stream));
@@ -456,10 +459,15 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     int* lists = reinterpret_cast<int*>(c.ws + l.adjl);
     int* counts = lists + 4 * size_t(c.s.M);
     const size_t M = size_t(c.s.M);
+    int* redo = lists + 5 * M;
     GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, c.stream));
-    if (ac.nc_p > 0)
+    if (ac.nc_p > 0) {
+      GG_HIP(launch_fill_u32(reinterpret_cast<unsigned*>(redo), c.s.M, 0u, c.stream));
       GG_TIMED("adjoint_path", launch_adjoint_path(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                   gpart, merges, l.MT, lists + 3 * M, counts + 3, c.stream));
+                                                   gpart, merges, l.MT, redo, lists + 3 * M, counts + 3,
+                                                   c.stream));
+      GG_TIMED("adjoint_relist", launch_adjoint_relist(ac, meta, c.s.M, redo, lists, counts, c.stream));
+    }
     if (ac.need_a)
       GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
                                                  ab, gpart, lists, counts + 0, c.stream));
@@ -820,7 +828,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     struct Cand {
       int K, TC, F;
     };
-    const Cand cands[8] = {{4, 0, 16}, {4, 0, 8}, {8, 0, 8}, {2, 0, 16},
+    const Cand cands[9] = {{4, 0, 16}, {4, 0, 12}, {4, 0, 8}, {8, 0, 8}, {2, 0, 16},
                            {2, 0, 32}, {4, 16, 0}, {2, 16, 0}, {2, 32, 0}};
     const int Rs_a[4] = {256, 512, 1024, 2048};
     const int Gs_a[4] = {4, 8, 16, 32};

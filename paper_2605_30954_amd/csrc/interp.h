@@ -361,7 +361,7 @@ __device__ inline typename VecT<T, K>::type run_program(const Src& prog,
   prefetch_operand<T, K>(cur.x, xl, rstride, pre);
   int pc = 0;
 #pragma unroll 1
-  while (!(cur.x & U_END)) {
+  while (cur.x != UOP_END_HDR) {
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
     const float c = f32_of(cur.y);

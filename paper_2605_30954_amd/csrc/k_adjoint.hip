@@ -55,8 +55,9 @@ struct AdjParams {
   int64_t span_rows;  // rows per span (common to every tier)
   int tape_cap;       // LDS tape entries per wave (tier C)
   int lane_consts;    // CC: constant columns per wave (register tiers)
-  const uint32_t* merges;  // [M][MT] merge ranges (path tier)
+  const uint32_t* merges;  // [M][MT] flush events (path tier)
   int MT;
+  int* redo;               // [M] path tier: set when an individual's partials are not finite
 };
 
 // Tier of an individual: -1 no gradient work (bad program, non-finite, b = 0
@@ -286,7 +287,7 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
   prefetch_operand<float, K>(cur.x, xl, rstride, pre);
   int pc = 0, tp = 0;
 #pragma unroll 1
-  while (!(cur.x & U_END)) {
+  while (cur.x != UOP_END_HDR) {
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
     operand_stage<float, K, D>(h, f32_of(cur.y), xl, rstride, acc, t, pre, st);
@@ -423,21 +424,23 @@ __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
 // Forward accumulation for a tree without a tape.  d p / d c_j is the product
 // of the local partials on the path from constant j to the root.  The
 // constants of any subtree are contiguous in postfix order, so every value
-// carries one "pending" factor per row: the product of the partials from the
-// subtree's last merge (a uop whose two operands both hold constants) up to
-// here, and a register array T holds, per constant, the product from the
-// constant up to that merge.  A uop with a constant in one operand only
-// multiplies that operand's pending factor by its partial; a merge folds each
-// operand's pending factor times its partial into T over the operand's
-// constant range (assigning when the operand is a single constant, which has
-// no entry yet) and restarts the pending factor at 1.  At the root,
-// d p / d c_j = pending * T[j] (T is unused with one constant).
-// The ranges of the merges come from the compile step, one descriptor per
-// merge in uop order (lane m of `mt` holds merge m).
+// carries one "pending" factor per row, the product of the partials since its
+// constants were last folded into a register array T (entry j: the product
+// from constant j up to that point).  A uop with a constant in one operand
+// only multiplies that operand's pending factor by its partial.  The pending
+// factor is folded into T over the operand's constant range at a merge (a uop
+// whose two operands both hold constants; each operand with its own partial)
+// and at the push of a value that holds constants, after which the factor
+// restarts at 1; a single constant's entry is assigned the first time.  At
+// the root, d p / d c_j = pending * T[j].
+// The compile step lists the flush events in uop order (lane m of `mt` holds
+// event m): each side is lo | n << 7 | assign << 14, a merge's src side in
+// bits 15..29.
 template <int K, int NC>
-__device__ inline void path_flush(RegTape<K, NC>& T, uint32_t lo, uint32_t n,
+__device__ inline void path_flush(RegTape<K, NC>& T, uint32_t side,
                                   const typename VecT<float, K>::type& f) {
-  if (n == 1) {
+  const uint32_t lo = side & 127u, n = (side >> 7) & 127u;
+  if (side & (1u << 14)) {
     if (lo < uint32_t(NC)) T.put(int(lo), f);
     GG_BRANCH();
   } else {
@@ -453,24 +456,32 @@ __device__ inline typename VecT<float, K>::type run_forward_path(
     const Src& prog, uint32_t mt, const float* __restrict__ xt, int rstride, int lrow,
     RegTape<K, NC>& T, typename VecT<float, K>::type& p) {
   using V = typename VecT<float, K>::type;
-  Slots<V, D> st, ps;  // values and pending factors of the pushed subtrees
-  V acc = 0.0f, t = 0.0f, pre = 0.0f, q = 1.0f;
+  Slots<V, D> st;
+  V acc = 0.0f, t = 0.0f, pre = 0.0f;
   p = 1.0f;
+  // a lone constant whose value is never pushed is never flushed: its entry
+  // stays 1 (with two or more constants every entry is written by a merge)
+  T.put(0, V(1.0f));
   int mi = 0;
   const float* __restrict__ xl = xt + lrow;
   uint2 cur = prog.at(0);
   prefetch_operand<float, K>(cur.x, xl, rstride, pre);
   int pc = 0;
 #pragma unroll 1
-  while (!(cur.x & U_END)) {
+  while (cur.x != UOP_END_HDR) {
     const uint2 nxt = prog.at(pc + 1);
     const uint32_t h = cur.x;
     const float c = f32_of(cur.y);
-    // operands and their pending factors (a constant starts at 1)
+    // operands (a constant and a popped value start with pending factor 1)
     if (h & (U_LDV | U_LDC)) {
       if (h & HDR_PUSH) {
         st.put(uop_push_slot(h), acc);
-        ps.put(uop_push_slot(h), p);
+        if (h & U_PUSHC) {
+          const uint32_t ev = uint32_t(__builtin_amdgcn_readlane(int(mt), mi));
+          ++mi;
+          path_flush<K, NC>(T, ev, p);
+          GG_BRANCH();
+        }
         GG_BRANCH();
       }
       if (h & U_LDV) {
@@ -488,14 +499,12 @@ __device__ inline typename VecT<float, K>::type run_forward_path(
       GG_BRANCH();
     } else if (h & U_SC) {
       t = bcast<float, K>(c);
-      q = 1.0f;
       GG_BRANCH();
     } else if (h & U_TX2) {
       t = lds_rows<float, K>(xl + uop_arg2(h) * rstride);
       GG_BRANCH();
     } else if (h & U_SP) {
       st.get(uop_arg2(h), t);
-      ps.get(uop_arg2(h), q);
       GG_BRANCH();
     }
     prefetch_operand<float, K>(nxt.x, xl, rstride, pre);
@@ -524,10 +533,10 @@ __device__ inline typename VecT<float, K>::type run_forward_path(
     }
     if (h & HDR_ADJ_ACC) {
       if (h & HDR_ADJ_SRC) {  // merge
-        const uint32_t md = uint32_t(__builtin_amdgcn_readlane(int(mt), mi));
+        const uint32_t ev = uint32_t(__builtin_amdgcn_readlane(int(mt), mi));
         ++mi;
-        path_flush<K, NC>(T, md & 255u, (md >> 8) & 255u, fa * p);
-        path_flush<K, NC>(T, (md >> 16) & 255u, md >> 24, fs * q);
+        path_flush<K, NC>(T, ev & 0x7fffu, fa * p);
+        path_flush<K, NC>(T, ev >> 15, fs);
         p = 1.0f;
         GG_BRANCH();
       } else {
@@ -536,7 +545,7 @@ __device__ inline typename VecT<float, K>::type run_forward_path(
       }
       GG_BRANCH();
     } else if (h & HDR_ADJ_SRC) {
-      p = fs * q;
+      p = fs;  // the src operand's pending factor is 1
       GG_BRANCH();
     }
     cur = nxt;
@@ -771,14 +780,10 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
           const auto v = run_forward_path<K, D, NC>(prog, mt, xs, R, lrow, T, pf);
           const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid) * pf;
           const int kv = max(0, min(K, nvalid - lrow));
-          if (nc == 1) {
-            sink.template add<typename VecT<float, K>::type, K>(0u, g, kv);
-          } else {
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
-              if (j >= nc) break;  // wave-uniform
-              sink.template add<typename VecT<float, K>::type, K>(uint32_t(j), g * T.get(j), kv);
-            }
+          for (int j = 0; j < NC; ++j) {
+            if (j >= nc) break;  // wave-uniform
+            sink.template add<typename VecT<float, K>::type, K>(uint32_t(j), g * T.get(j), kv);
           }
         }
         reduce_columns<W>(lacc, nc, lane, gacc + size_t(jj) * p.C_max);
@@ -789,6 +794,11 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
     }
     __syncthreads();
     adj_write(p, it.span, base, Gn, gacc);
+    // a partial that is not finite may be an overflow of an intermediate
+    // product that the reverse sweep does not form: the individual is
+    // differentiated again by the tape tiers, which overwrite its partials
+    for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x)
+      if (!isfinite(gacc[j])) p.redo[p.list[base + j / p.C_max]] = 1;
   }
 }
 
@@ -921,16 +931,76 @@ static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, co
                             int U_stride, const ProgMeta* meta, int M, int C_max,
                             const DataArgs& d, const double* stats, const double* ab,
                             double* gpart, const int* list, const int* count,
-                            const uint32_t* merges = nullptr, int MT = 0) {
+                            const uint32_t* merges = nullptr, int MT = 0, int* redo = nullptr) {
   return AdjParams{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
                    list, count, c.R, c.G, n_groups, a.n_spans, a.span_rows, a.tape_cap,
-                   a.lane_consts, merges, MT};
+                   a.lane_consts, merges, MT, redo};
 }
 
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                     int* lists, int* counts, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_partition, dim3(1), dim3(kPartThreads), 0, s, meta, ab, M, a.tc_a,
                      a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.nc_p, lists, counts);
+  return hipGetLastError();
+}
+
+// Path tier fallback: the individuals flagged in redo[] (few) are appended,
+// in batch order, to the list of tape tier B (tape of at most tcB entries and
+// at most CC constants; its waves share each individual, so a lone one still
+// keeps a block busy) or else tier C.  One block; a block-wide scan keeps the
+// order deterministic.
+__global__ __launch_bounds__(kPartThreads) void k_adj_relist(const ProgMeta* __restrict__ meta, int M,
+                                                             int tcB, int CC,
+                                                             const int* __restrict__ redo,
+                                                             int* __restrict__ lists,
+                                                             int* __restrict__ counts) {
+  __shared__ int sc[2][kPartThreads];
+  __shared__ int base[2];
+  const int t = threadIdx.x;
+  const int chunk = (M + kPartThreads - 1) / kPartThreads;
+  const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
+  auto tier_of = [&](int i) {
+    const ProgMeta& pm = meta[i];
+    return (pm.n_const <= CC && pm.n_tape <= tcB) ? 0 : 1;
+  };
+  int n[2] = {0, 0};
+  for (int i = lo; i < hi; ++i)
+    if (redo[i]) ++n[tier_of(i)];
+  sc[0][t] = n[0];
+  sc[1][t] = n[1];
+  if (t == 0) {
+    base[0] = counts[1];
+    base[1] = counts[2];
+  }
+  __syncthreads();
+  for (int o = 1; o < kPartThreads; o <<= 1) {  // inclusive Hillis-Steele scan
+    int a0 = 0, a1 = 0;
+    if (t >= o) {
+      a0 = sc[0][t - o];
+      a1 = sc[1][t - o];
+    }
+    __syncthreads();
+    sc[0][t] += a0;
+    sc[1][t] += a1;
+    __syncthreads();
+  }
+  int w0 = base[0] + sc[0][t] - n[0], w1 = base[1] + sc[1][t] - n[1];
+  for (int i = lo; i < hi; ++i) {
+    if (!redo[i]) continue;
+    if (tier_of(i) == 0) lists[size_t(M) + w0++] = i;
+    else lists[size_t(2) * M + w1++] = i;
+  }
+  __syncthreads();
+  if (t == kPartThreads - 1) {
+    counts[1] = base[0] + sc[0][t];
+    counts[2] = base[1] + sc[1][t];
+  }
+}
+
+hipError_t launch_adjoint_relist(const AdjPlan& a, const ProgMeta* meta, int M, const int* redo,
+                                 int* lists, int* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_relist, dim3(1), dim3(kPartThreads), 0, s, meta, M, a.tc_b,
+                     a.lane_consts, redo, lists, counts);
   return hipGetLastError();
 }
 
@@ -979,12 +1049,12 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
 hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                                const double* stats, const double* ab, double* gpart,
-                               const uint32_t* merges, int MT, const int* list, const int* count,
-                               hipStream_t s) {
+                               const uint32_t* merges, int MT, int* redo, const int* list,
+                               const int* count, hipStream_t s) {
   const TileCfg& c = a.path;
   const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
-                                  gpart, list, count, merges, MT);
-  if (c.W != 4 || MT < 1) return hipErrorInvalidValue;
+                                  gpart, list, count, merges, MT, redo);
+  if (c.W != 4 || MT < 1 || !redo) return hipErrorInvalidValue;
   if (c.K == 4 && a.nc_p == 16 && c.D == 4) return path_impl<4, 4, 4, 16>(c, ap, s);
   if (c.K == 4 && a.nc_p == 16 && c.D == 8) return path_impl<4, 8, 4, 16>(c, ap, s);
   if (c.K == 8 && a.nc_p == 8 && c.D == 4) return path_impl<8, 4, 4, 8>(c, ap, s);
@@ -993,6 +1063,8 @@ hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride
   if (c.K == 2 && a.nc_p == 32 && c.D == 8) return path_impl<2, 8, 4, 32>(c, ap, s);
   if (c.K == 4 && a.nc_p == 8 && c.D == 4) return path_impl<4, 4, 4, 8>(c, ap, s);
   if (c.K == 4 && a.nc_p == 8 && c.D == 8) return path_impl<4, 8, 4, 8>(c, ap, s);
+  if (c.K == 4 && a.nc_p == 12 && c.D == 4) return path_impl<4, 4, 4, 12>(c, ap, s);
+  if (c.K == 4 && a.nc_p == 12 && c.D == 8) return path_impl<4, 8, 4, 12>(c, ap, s);
   if (c.K == 2 && a.nc_p == 16 && c.D == 4) return path_impl<2, 4, 4, 16>(c, ap, s);
   if (c.K == 2 && a.nc_p == 16 && c.D == 8) return path_impl<2, 8, 4, 16>(c, ap, s);
   return hipErrorInvalidValue;  // no kernel instantiated for this launch shape

@@ -99,6 +99,7 @@ struct CompileLds {
   int16_t clo[kLMax], cnum[kLMax];  // constants of the subtree: ordinals [clo, clo + cnum)
   int8_t sym[kLMax];
   uint8_t need[kLMax], hasc[kLMax], stt[kLMax];
+  uint8_t written[kLMax];  // path mode: the subtree's constant entries have been written
 };
 
 __device__ inline int arity_of(int s) {
@@ -141,20 +142,47 @@ __device__ inline int uop_cost(uint32_t op) {
 }
 
 // Emits uops of one program; state lives in LDS, one active lane.
+// Path forward mode keeps, per constant j, an entry T[j]: the product of the
+// local partials from constant j up to the last point where its subtree was
+// folded into T ("flushed": at a merge, a uop whose two operands both hold
+// constants, and at the push of a value that holds constants).  The compile
+// step lists these flush events in uop order, one 32-bit descriptor each:
+//   side A [0:15): lo (7 bits) | n (7 bits) << 7 | assign << 14
+//   side S [15:30): the same for a merge's src operand (unused for a push)
+// where [lo, lo + n) is the operand's constant range (contiguous in postfix
+// order) and `assign` says the entry has never been written (a single
+// constant): T[lo] = f instead of T[e] *= f.  Ranges need nc <= 127.
+__device__ inline uint32_t flush_side(int lo, int n, bool assign) {
+  return uint32_t(lo & 127) | (uint32_t(n & 127) << 7) | (assign ? 1u << 14 : 0u);
+}
+
+// Emits uops of one program; state lives in LDS, one active lane.
 struct Emitter {
   uint2* out;
   const float* cs;
-  uint32_t* merges;  // one descriptor per merge, in uop order
-  int merge_cap = 0, n_merge = 0;
+  CompileLds* L;
+  uint32_t* events;  // flush events, in uop order
+  int event_cap = 0, n_event = 0;
   int n = 0, cap = 0, tape = 0, cost = 0;
   bool push_pending = false;
   uint32_t push_slot = 0;
+  int push_node = -1;  // the subtree pushed by the next uop
   bool bad = false;
 
+  __device__ inline void event(uint32_t d) {
+    if (n_event < event_cap) events[n_event] = d;
+    ++n_event;
+  }
   __device__ inline void emit(uint32_t hdr, uint32_t payload) {
     if (push_pending) {
       if (uop_load(hdr) == LD_NONE) bad = true;  // a pushed subtree starts with a load
-      hdr = with_push(hdr, push_slot);
+      const int pn = push_node;
+      const bool hc = L->hasc[pn] != 0;
+      hdr = with_push(hdr, push_slot, hc);
+      if (hc) {  // the pushed value's pending factor is folded into T
+        event(flush_side(L->clo[pn], L->cnum[pn], !L->written[pn]));
+        L->written[pn] = 1;
+      }
       push_pending = false;
     }
     if (n >= cap) {
@@ -165,14 +193,11 @@ struct Emitter {
     tape += tape_acc(hdr) + tape_src(hdr);
     cost += uop_cost(uop_op(hdr));
   }
-  // the uop just emitted merges two operands that both hold constants: their
-  // constant ordinal ranges (each operand's constants are contiguous in
-  // postfix order)
-  __device__ inline void merge(int loA, int nA, int loS, int nS) {
-    if (n_merge < merge_cap)
-      merges[n_merge] = uint32_t(loA) | (uint32_t(nA) << 8) | (uint32_t(loS) << 16) |
-                        (uint32_t(nS) << 24);
-    ++n_merge;
+  // the uop just emitted merges operand subtree a (acc) and b (src), both
+  // holding constants; the result's entries are all written
+  __device__ inline void merge(int a, int b) {
+    event(flush_side(L->clo[a], L->cnum[a], !L->written[a]) |
+          (flush_side(L->clo[b], L->cnum[b], !L->written[b]) << 15));
   }
 };
 
@@ -223,6 +248,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
     L.ci[t] = -1;
     L.clo[t] = int16_t(nc);
     L.cnum[t] = 0;
+    L.written[t] = 0;
     if (ar == 0) {
       if (s == GPGOMEA_SYM_CONST) {
         if (nc >= C_max) bad = true;
@@ -272,8 +298,9 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
   Emitter E;
   E.out = out;
   E.cs = cs;
-  E.merges = merges + size_t(i) * MT;
-  E.merge_cap = MT;
+  E.L = &L;
+  E.events = merges + size_t(i) * MT;
+  E.event_cap = MT;
   E.cap = U_stride - 2;
   int maxsp = 0;
   if (!bad) {
@@ -309,6 +336,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
             continue;
           }
           E.emit(make_hdr(un_uop(s), SRC_NONE, 0, LD_NONE, 0) | (L.hasc[c] ? HDR_ADJ_ACC : 0), 0);
+          L.written[n] = L.written[c];
         } else {
           uint32_t k, a, pay;
           bool hc;
@@ -329,7 +357,8 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
         if (ka == SRC_CONST && kb == SRC_CONST) {
           E.emit(make_hdr(UOP_NOP, SRC_NONE, 0, LD_CONST, aa) | HDR_ADJ_ACC, pa);
           E.emit(make_hdr(bin_uop(s, false), SRC_CONST, ab, LD_NONE, 0) | HDR_ADJ_ACC | HDR_ADJ_SRC, pb);
-          E.merge(L.ci[a], 1, L.ci[b], 1);
+          E.merge(a, b);
+          L.written[n] = 1;
         } else if (ka == SRC_CONST) {  // load the variable b, constant a is the src: a op b
           E.emit(make_hdr(bin_uop(s, true), SRC_CONST, aa, LD_VAR, ab) | HDR_ADJ_SRC, pa);
         } else {  // load variable a; b is a variable or a constant
@@ -354,7 +383,12 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
         E.emit(make_hdr(bin_uop(s, ta), k, ar2, LD_NONE, 0) | (L.hasc[nt] ? HDR_ADJ_ACC : 0) |
                    (hc ? HDR_ADJ_SRC : 0),
                pay);
-        if (L.hasc[nt] && hc) E.merge(L.clo[nt], L.cnum[nt], L.ci[tt], 1);
+        if (L.hasc[nt] && hc) {
+          E.merge(nt, tt);
+          L.written[n] = 1;
+        } else {
+          L.written[n] = L.written[nt];  // the terminal holds no entry
+        }
         --top;
         continue;
       }
@@ -371,6 +405,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
       if (st == 1) {
         L.stt[top] = 2;
         E.push_pending = true;
+        E.push_node = first;
         E.push_slot = uint32_t(dsp);
         ++dsp;
         if (dsp > maxsp) maxsp = dsp;
@@ -385,8 +420,12 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
       E.emit(make_hdr(bin_uop(s, !b_first), SRC_POP, uint32_t(dsp), LD_NONE, 0) |
                  (L.hasc[second] ? HDR_ADJ_ACC : 0) | (L.hasc[first] ? HDR_ADJ_SRC : 0),
              0);
-      if (L.hasc[second] && L.hasc[first])
-        E.merge(L.clo[second], L.cnum[second], L.clo[first], L.cnum[first]);
+      if (L.hasc[second] && L.hasc[first]) {
+        E.merge(second, first);
+        L.written[n] = 1;
+      } else {
+        L.written[n] = L.written[second] | L.written[first];
+      }
       --top;
     }
   }
@@ -404,7 +443,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
     pm.n_tape = E.tape;
     pm.n_const = nc;
     pm.cost = E.cost;
-    pm.n_merge = E.n_merge;
+    pm.n_merge = E.n_event;
   }
   pm.mu = 0.0f;
   meta[i] = pm;

@@ -82,7 +82,7 @@ struct AdjPlan {
   int tc_a = 16, tc_b = 32;  // register tape entries of tiers A and B
   int lane_consts = 16;      // per-lane constant columns of the register tiers
   int tape_cap = 1;          // LDS tape entries per wave of tier C
-  bool need_b = true;        // some program of this shape may fall in tier B
+  bool need_b = true;        // ... in tier B (or fall back to it from the path tier)
   bool need_wide = true;     // ... in tier C
   int nc_p = 16;             // path tier: programs with <= nc_p constants (0: none)
   bool need_a = true;        // some program of this shape may fall in tier A
@@ -100,11 +100,16 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
                               const int* list, const int* count, hipStream_t s);
+// path tier; redo[i] is set for an individual whose partials are not finite
+// (zero redo[] before)
 hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                                const double* stats, const double* ab, double* gpart,
-                               const uint32_t* merges, int MT, const int* list, const int* count,
-                               hipStream_t s);
+                               const uint32_t* merges, int MT, int* redo, const int* list,
+                               const int* count, hipStream_t s);
+// appends the individuals flagged in redo[] to the lists of tiers B and C
+hipError_t launch_adjoint_relist(const AdjPlan& a, const ProgMeta* meta, int M, const int* redo,
+                                 int* lists, int* counts, hipStream_t s);
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,

@@ -14,10 +14,11 @@
 // One uop = uint2 {hdr, payload}; payload carries a constant's float bits.
 // The header is laid out for the interpreters' scalar dispatch: every
 // decision they take is a single-bit test (s_bitcmp + branch), and the
-// operand fields need no further decoding.
+// operand fields need no further decoding.  The END uop's header is exactly
+// UOP_END (no flag set), so the loop test is one compare.
 //   hdr[0:4)   op (UOP_*)
 //   hdr[4]     CHEAP: op is ADD, SUB, RSUB or MUL
-//   hdr[5]     END
+//   hdr[5]     PUSHC: the pushed value (PUSH) holds a constant
 //   hdr[6]     LDV: load prefix is a variable (acc <- x[var1] before the op)
 //   hdr[7]     LDC: load prefix is a constant (acc <- c); the load prefix is
 //              the first leaf of a subtree
@@ -66,7 +67,7 @@ enum : uint32_t { SRC_NONE = 0, SRC_VAR = 1, SRC_CONST = 2, SRC_POP = 3 };
 enum : uint32_t { LD_NONE = 0, LD_VAR = 1, LD_CONST = 2 };
 
 constexpr uint32_t U_CHEAP = 1u << 4;
-constexpr uint32_t U_END = 1u << 5;
+constexpr uint32_t U_PUSHC = 1u << 5;
 constexpr uint32_t U_LDV = 1u << 6;
 constexpr uint32_t U_LDC = 1u << 7;
 constexpr uint32_t HDR_PUSH = 1u << 8;
@@ -78,7 +79,7 @@ constexpr uint32_t U_SV = U_TPRE | U_TX2;   // src is a variable
 constexpr uint32_t U_V1 = U_LDV | U_TPRE;   // the uop reads a first variable
 constexpr uint32_t HDR_ADJ_ACC = 1u << 13;
 constexpr uint32_t HDR_ADJ_SRC = 1u << 14;
-constexpr uint32_t UOP_END_HDR = uint32_t(UOP_END) | U_END;
+constexpr uint32_t UOP_END_HDR = uint32_t(UOP_END);
 
 __host__ __device__ constexpr inline uint32_t uop_op(uint32_t h) { return h & 15u; }
 __host__ __device__ constexpr inline uint32_t uop_push_slot(uint32_t h) { return (h >> 15) & 7u; }
@@ -102,7 +103,7 @@ __host__ __device__ constexpr inline uint32_t uop_load_arg(uint32_t h) {
 __host__ __device__ constexpr inline uint32_t make_hdr(uint32_t op, uint32_t src, uint32_t srcarg,
                                                        uint32_t load, uint32_t loadarg) {
   const uint32_t flags = (op >= UOP_ADD && op <= UOP_MUL ? U_CHEAP : 0u) |
-                         (op == UOP_END ? U_END : 0u) | (load == LD_VAR ? U_LDV : 0u) |
+                         (load == LD_VAR ? U_LDV : 0u) |
                          (load == LD_CONST ? U_LDC : 0u) |
                          (src == SRC_VAR ? (load == LD_VAR ? U_TX2 : U_TPRE) : 0u) |
                          (src == SRC_CONST ? U_SC : 0u) | (src == SRC_POP ? U_SP : 0u);
@@ -113,8 +114,8 @@ __host__ __device__ constexpr inline uint32_t make_hdr(uint32_t op, uint32_t src
                                                              : 0u;
   return op | flags | ((var1 & 63u) << 18) | ((arg2 & 255u) << 24);
 }
-__host__ __device__ constexpr inline uint32_t with_push(uint32_t h, uint32_t slot) {
-  return h | HDR_PUSH | ((slot & 7u) << 15);
+__host__ __device__ constexpr inline uint32_t with_push(uint32_t h, uint32_t slot, bool has_const) {
+  return h | HDR_PUSH | (has_const ? U_PUSHC : 0u) | ((slot & 7u) << 15);
 }
 
 // Adjoint tape rule: how many per-row factors a uop stores in the forward
