@@ -69,7 +69,8 @@ int adj_span_cap(const Shape& s) {
 }
 
 struct Layout {
-  size_t stats, yscr, meta, uops, merges, ab, part, plain_part, ticket, gpart, adjl, tune, total;
+  size_t stats, yscr, meta, uops, merges, ab, part, plain_part, ticket, gpart, adjl, redo_span, tune,
+      total;
   int U_stride;
   int MT;  // merge descriptors per program
 };
@@ -102,6 +103,8 @@ Layout layout_of(const Shape& s) {
   l.adjl = o;  // adjoint tier lists [4][M] + counts [4] + path redo flags [M] at 5M, or
                // per-individual counts [M][4] + a list
   o = align256(o + size_t(s.M) * 8 * sizeof(int32_t) + 64);
+  l.redo_span = o;  // path tier fallback: [M][n_spans] bytes
+  o = align256(o + size_t(s.M) * kMaxAdjSpans);
   l.tune = o;  // outputs of the autotuner's trial calls: fitness, grad, status
   o = align256(o + size_t(s.M) * (std::max(s.C_max, 1) + 2) * sizeof(double));
   l.total = o;
@@ -438,13 +441,15 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
         const int* ci = pcounts + 4 * size_t(i);
         if (one.need_a)
           GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
-                                                       stats, abi, gi, list0, ci + 0, c.stream));
+                                                       stats, abi, gi, list0, ci + 0, nullptr, nullptr,
+                                                       c.stream));
         if (one.need_b)
           GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 1, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
-                                                       stats, abi, gi, list0, ci + 1, c.stream));
+                                                       stats, abi, gi, list0, ci + 1, nullptr, nullptr,
+                                                       c.stream));
         if (one.need_wide)
           GG_TIMED("plain_adjoint", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
-                                                       abi, gi, list0, ci + 2, c.stream));
+                                                       abi, gi, list0, ci + 2, nullptr, nullptr, c.stream));
       }
       GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
                                                      c.s.flags, c.status, c.grad, c.stream));
@@ -460,23 +465,26 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     int* counts = lists + 4 * size_t(c.s.M);
     const size_t M = size_t(c.s.M);
     int* redo = lists + 5 * M;
+    uint8_t* redo_span = reinterpret_cast<uint8_t*>(c.ws + l.redo_span);
+    int* rd = ac.nc_p > 0 ? redo : nullptr;  // the tape tiers' fallback flags
+    uint8_t* rs = ac.nc_p > 0 ? redo_span : nullptr;
     GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, c.stream));
     if (ac.nc_p > 0) {
       GG_HIP(launch_fill_u32(reinterpret_cast<unsigned*>(redo), c.s.M, 0u, c.stream));
       GG_TIMED("adjoint_path", launch_adjoint_path(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                   gpart, merges, l.MT, redo, lists + 3 * M, counts + 3,
-                                                   c.stream));
+                                                   gpart, merges, l.MT, redo, redo_span, lists + 3 * M,
+                                                   counts + 3, c.stream));
       GG_TIMED("adjoint_relist", launch_adjoint_relist(ac, meta, c.s.M, redo, lists, counts, c.stream));
     }
     if (ac.need_a)
       GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
-                                                 ab, gpart, lists, counts + 0, c.stream));
+                                                 ab, gpart, lists, counts + 0, nullptr, nullptr, c.stream));
     if (ac.need_b)
       GG_TIMED("adjoint_reg_b", launch_adjoint_reg(ac, 1, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
-                                                   ab, gpart, lists + M, counts + 1, c.stream));
+                                                   ab, gpart, lists + M, counts + 1, rd, rs, c.stream));
     if (ac.need_wide)
       GG_TIMED("adjoint_lds", launch_adjoint_lds(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                 gpart, lists + 2 * M, counts + 2, c.stream));
+                                                 gpart, lists + 2 * M, counts + 2, rd, rs, c.stream));
     GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab,
                                                    c.s.flags, c.status, c.grad, c.stream));
   }
@@ -830,7 +838,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     };
     const Cand cands[9] = {{4, 0, 16}, {4, 0, 12}, {4, 0, 8}, {8, 0, 8}, {2, 0, 16},
                            {2, 0, 32}, {4, 16, 0}, {2, 16, 0}, {2, 32, 0}};
-    const int Rs_a[4] = {256, 512, 1024, 2048};
+    const int Rs_a[5] = {256, 512, 768, 1024, 2048};
     const int Gs_a[4] = {4, 8, 16, 32};
     Tuned best_a{0, 0, 0, 0, 0};
     float best_a_ms = 1e30f;

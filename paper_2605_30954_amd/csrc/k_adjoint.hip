@@ -58,7 +58,15 @@ struct AdjParams {
   const uint32_t* merges;  // [M][MT] flush events (path tier)
   int MT;
   int* redo;               // [M] path tier: set when an individual's partials are not finite
+  uint8_t* redo_span;      // [M][n_spans] ... and for which spans; the tape tiers then
+                           // redo only those spans of a flagged individual
 };
+
+// A tape tier skips span s of individual i when i fell back from the path
+// tier and the path tier's partials of span s are finite (they are kept).
+__device__ inline bool keep_path_span(const AdjParams& p, int i, int span) {
+  return p.redo != nullptr && p.redo[i] != 0 && p.redo_span[size_t(i) * p.n_spans + span] == 0;
+}
 
 // Tier of an individual: -1 no gradient work (bad program, non-finite, b = 0
 // or no constant), 3 path forward mode (at most ncP constants), 0 register
@@ -600,10 +608,14 @@ __device__ inline typename VecT<float, K>::type adj_seed(const typename VecT<flo
 }
 
 // Write the partials of this group (individuals list[base .. base+Gn)).
+// A tape tier (FALLBACK = true) leaves alone the spans of a fallen-back
+// individual that the path tier got right; the path tier writes every span.
+template <bool FALLBACK = true>
 __device__ inline void adj_write(const AdjParams& p, int span, int base, int Gn, const double* gacc) {
   for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x) {
     const int jj = j / p.C_max, c = j - jj * p.C_max;
     const int i = p.list[base + jj];
+    if (FALLBACK && keep_path_span(p, i, span)) continue;
     p.gpart[(size_t(i) * p.n_spans + span) * p.C_max + c] = gacc[j];
   }
 }
@@ -689,7 +701,8 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
         const double s1 = p.ab[size_t(i) * 2 + 1];
         const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
-        for (int b = SPLIT ? wv : 0; b < nbatch; b += SPLIT ? W : 1) {
+        const int nb = keep_path_span(p, i, it.span) ? 0 : nbatch;
+        for (int b = SPLIT ? wv : 0; b < nb; b += SPLIT ? W : 1) {
           const int lrow = b * BR + lane * K;
           RegTape<K, TC> tape;
           const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
@@ -793,12 +806,17 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
       }
     }
     __syncthreads();
-    adj_write(p, it.span, base, Gn, gacc);
+    adj_write<false>(p, it.span, base, Gn, gacc);
     // a partial that is not finite may be an overflow of an intermediate
-    // product that the reverse sweep does not form: the individual is
-    // differentiated again by the tape tiers, which overwrite its partials
-    for (int j = threadIdx.x; j < Gn * p.C_max; j += blockDim.x)
-      if (!isfinite(gacc[j])) p.redo[p.list[base + j / p.C_max]] = 1;
+    // product that the reverse sweep does not form: that span of the
+    // individual is differentiated again by the tape tiers
+    for (int jj = threadIdx.x; jj < Gn; jj += blockDim.x) {
+      bool bad = false;
+      for (int c = 0; c < p.C_max; ++c) bad = bad || !isfinite(gacc[size_t(jj) * p.C_max + c]);
+      const int i = p.list[base + jj];
+      p.redo_span[size_t(i) * p.n_spans + it.span] = bad ? 1 : 0;
+      if (bad) p.redo[i] = 1;
+    }
   }
 }
 
@@ -842,6 +860,7 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
       const int nbatch = (nvalid + BR - 1) / BR;
       for (int jj = 0; jj < Gn; ++jj) {  // uniform over the block
         const int i = __builtin_amdgcn_readfirstlane(p.list[base + jj]);
+        if (keep_path_span(p, i, it.span)) continue;
         const ProgMeta pm = p.meta[i];
         if (__builtin_amdgcn_readfirstlane(pm.n_tape) > p.tape_cap) continue;  // cannot happen
         const double s1 = p.ab[size_t(i) * 2 + 1];
@@ -931,10 +950,11 @@ static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, co
                             int U_stride, const ProgMeta* meta, int M, int C_max,
                             const DataArgs& d, const double* stats, const double* ab,
                             double* gpart, const int* list, const int* count,
-                            const uint32_t* merges = nullptr, int MT = 0, int* redo = nullptr) {
+                            const uint32_t* merges = nullptr, int MT = 0, int* redo = nullptr,
+                            uint8_t* redo_span = nullptr) {
   return AdjParams{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
                    list, count, c.R, c.G, n_groups, a.n_spans, a.span_rows, a.tape_cap,
-                   a.lane_consts, merges, MT, redo};
+                   a.lane_consts, merges, MT, redo, redo_span};
 }
 
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
@@ -1029,11 +1049,12 @@ hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, con
 hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
-                              const int* list, const int* count, hipStream_t s) {
+                              const int* list, const int* count, int* redo,
+                              uint8_t* redo_span, hipStream_t s) {
   const TileCfg& c = tier == 0 ? a.reg : a.reg_b;
   const int TC = tier == 0 ? a.tc_a : a.tc_b;
   const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
-                                  gpart, list, count);
+                                  gpart, list, count, nullptr, 0, redo, redo_span);
   const int CC = a.lane_consts;
   const bool split = tier == 1;  // tier B: few individuals, the waves share each one
   if (c.W != 4) return hipErrorInvalidValue;
@@ -1049,12 +1070,12 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
 hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                                const double* stats, const double* ab, double* gpart,
-                               const uint32_t* merges, int MT, int* redo, const int* list,
-                               const int* count, hipStream_t s) {
+                               const uint32_t* merges, int MT, int* redo, uint8_t* redo_span,
+                               const int* list, const int* count, hipStream_t s) {
   const TileCfg& c = a.path;
   const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
-                                  gpart, list, count, merges, MT, redo);
-  if (c.W != 4 || MT < 1 || !redo) return hipErrorInvalidValue;
+                                  gpart, list, count, merges, MT, redo, redo_span);
+  if (c.W != 4 || MT < 1 || !redo || !redo_span) return hipErrorInvalidValue;
   if (c.K == 4 && a.nc_p == 16 && c.D == 4) return path_impl<4, 4, 4, 16>(c, ap, s);
   if (c.K == 4 && a.nc_p == 16 && c.D == 8) return path_impl<4, 8, 4, 16>(c, ap, s);
   if (c.K == 8 && a.nc_p == 8 && c.D == 4) return path_impl<8, 4, 4, 8>(c, ap, s);
@@ -1073,10 +1094,11 @@ hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
-                              const int* list, const int* count, hipStream_t s) {
+                              const int* list, const int* count, int* redo, uint8_t* redo_span,
+                              hipStream_t s) {
   const TileCfg& w = a.wide;
   const AdjParams ap = adj_params(a, w, w.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
-                                  gpart, list, count);
+                                  gpart, list, count, nullptr, 0, redo, redo_span);
   if (w.D != 8) return hipErrorInvalidValue;
   if (w.K == 2 && w.W == 4) return lds_impl<2, 8, 4>(w, ap, s);
   if (w.K == 2 && w.W == 2) return lds_impl<2, 8, 2>(w, ap, s);

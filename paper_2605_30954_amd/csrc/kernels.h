@@ -95,25 +95,30 @@ hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, cons
 // Plain form: counts[4i + tier] = 1 for individual i's tier, list0[0] = 0.
 hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                      int* counts, int* list0, hipStream_t s);
-// gradient partials gpart[i][span][C_max] of the individuals list[0 .. *count)
+// gradient partials gpart[i][span][C_max] of the individuals list[0 .. *count);
+// with redo (may be null), an individual that fell back from the path tier
+// is redone only on the spans flagged in redo_span
 hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
-                              const int* list, const int* count, hipStream_t s);
-// path tier; redo[i] is set for an individual whose partials are not finite
-// (zero redo[] before)
+                              const int* list, const int* count, int* redo,
+                              uint8_t* redo_span, hipStream_t s);
+// path tier; redo[i] is set for an individual with a partial that is not
+// finite (zero redo[] before) and redo_span[i][s] says which spans (written
+// for every span of every individual of the tier)
 hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                                const double* stats, const double* ab, double* gpart,
-                               const uint32_t* merges, int MT, int* redo, const int* list,
-                               const int* count, hipStream_t s);
+                               const uint32_t* merges, int MT, int* redo, uint8_t* redo_span,
+                               const int* list, const int* count, hipStream_t s);
 // appends the individuals flagged in redo[] to the lists of tiers B and C
 hipError_t launch_adjoint_relist(const AdjPlan& a, const ProgMeta* meta, int M, const int* redo,
                                  int* lists, int* counts, hipStream_t s);
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
-                              const int* list, const int* count, hipStream_t s);
+                              const int* list, const int* count, int* redo, uint8_t* redo_span,
+                              hipStream_t s);
 hipError_t launch_grad_finalize(const ProgMeta* meta, int M, int C_max, const double* gpart,
                                 int n_spans, const double* stats, const double* ab,
                                 uint32_t flags, const int8_t* status, double* grad,
