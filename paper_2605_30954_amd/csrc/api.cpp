@@ -179,7 +179,7 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
 }
 
 // Adjoint plan.  Path tier: programs with at most NC constants in path
-// forward mode, (K, NC) = (4, 16) unless tuned to (4, 12), (4, 8), (8, 8),
+// forward mode, (K, NC) = (4, 12) unless tuned to (4, 16), (4, 8), (8, 8),
 // (2, 16) or (2, 32).
 // Tier A: K rows per lane with a TC-entry register tape, (K, TC) = (4, 16)
 // unless tuned (without a path tier) to (2, 16) or (2, 32).  W = 4 waves; a
@@ -204,7 +204,7 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   pt.NP = r.NP = uop_pairs(s.L_max);
   pt.W = r.W = 4;
   pt.K = 4;
-  a.nc_p = 16;
+  a.nc_p = 12;  // (4, 12) is the largest variant that keeps three waves per SIMD
   pt.G = 16;
   pt.R = 1024;
   r.K = 4;

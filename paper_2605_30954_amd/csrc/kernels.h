@@ -84,7 +84,7 @@ struct AdjPlan {
   int tape_cap = 1;          // LDS tape entries per wave of tier C
   bool need_b = true;        // ... in tier B (or fall back to it from the path tier)
   bool need_wide = true;     // ... in tier C
-  int nc_p = 16;             // path tier: programs with <= nc_p constants (0: none)
+  int nc_p = 12;             // path tier: programs with <= nc_p constants (0: none)
   bool need_a = true;        // some program of this shape may fall in tier A
 };
 
