@@ -621,23 +621,20 @@ __device__ inline void adj_write(const AdjParams& p, int span, int base, int Gn,
 }
 
 // Per-wave column sums of the constant adjoints (binary64), added to acc[c].
+// Lane l converts its own entry of column c (consecutive words across the
+// lanes: conflict-free) and a fixed DPP tree sums the wave; one column at a
+// time, so the cost follows the program's constant count.
 template <int W>
 __device__ inline void reduce_columns(const float* lacc, int nc, int lane, double* acc) {
-  // the wave's column writes must land before lane c reads column c
+  // the wave's column writes must land before lane l reads entry l
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (lane < nc) {
-    const float* colc = lacc + lane * kColStride;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < 64; k += 4) {
-      a0 += double(colc[k]);
-      a1 += double(colc[k + 1]);
-      a2 += double(colc[k + 2]);
-      a3 += double(colc[k + 3]);
-    }
-    acc[lane] += (a0 + a1) + (a2 + a3);
+  for (int c = 0; c < nc; ++c) {  // wave-uniform
+    const double s = wave_sum(double(lacc[c * kColStride + lane]));
+    // every lane holds the same total and stores the same value (no divergent
+    // branch between the cross-lane sums of consecutive columns)
+    acc[c] += s;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
