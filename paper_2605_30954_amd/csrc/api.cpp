@@ -23,8 +23,8 @@ namespace gg {
 namespace {
 
 constexpr int kMaxSpans = 256;    // forward partial sums per individual (upper bound)
-constexpr int kMaxAdjSpans = 64;  // gradient partials per individual (upper bound)
-constexpr int64_t kAdjPartEntries = int64_t(1) << 22;  // cap on M x spans x C_max
+constexpr int kMaxAdjSpans = 256;  // gradient partials per individual (upper bound)
+constexpr int64_t kAdjPartEntries = int64_t(1) << 24;  // cap on M x spans x C_max (128 MB)
 constexpr int kPlainMaxBlocks = 1024;
 constexpr uint32_t kKnownFlags =
     GPGOMEA_LINEAR_SCALING | GPGOMEA_FP64_NODES | GPGOMEA_PLAIN | GPGOMEA_NO_GRAPH;
@@ -173,7 +173,9 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   }
   c.R = std::max(c.R, 64 * c.K);
   c.R = c.R / (64 * c.K) * (64 * c.K);
-  c.G = std::max(1, std::min(c.G, s.M));
+  // at most 64 programs per group: the forward kernel keeps a group's
+  // metadata in a 64-entry LDS table
+  c.G = std::max(1, std::min({c.G, s.M, 64}));
   finish_spans(c, s.M, s.N, kMaxSpans);
   return c;
 }
@@ -242,11 +244,16 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   const int64_t Nr = (s.N + 255) / 256 * 256;  // a multiple of every tier's batch
   if (Nr < lead.R) lead.R = int(Nr);
   lead.R = std::max(256, lead.R / 256 * 256);
-  lead.G = std::max(1, std::min(lead.G, s.M));
+  // at most 64 programs per group: the path kernel holds a group's list one
+  // entry per lane
+  lead.G = std::max(1, std::min({lead.G, s.M, 64}));
   lead.n_groups = (s.M + lead.G - 1) / lead.G;
-  // spans: enough blocks to fill the chip several times over
+  // spans: enough blocks to fill the chip many times over (about 16K work
+  // items, down to one row tile each).  The adjoint's cost per (program, tile)
+  // varies with the program, so small items keep the waves of the last rounds
+  // busy; each span costs one partial per (program, constant) in HBM.
   const int64_t tiles = (s.N + lead.R - 1) / lead.R;
-  int64_t want = (4096 + lead.n_groups - 1) / lead.n_groups;
+  int64_t want = (16384 + lead.n_groups - 1) / lead.n_groups;
   want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, int64_t(span_cap)}));
   lead.tiles_per_span = int((tiles + want - 1) / want);
   a.span_rows = int64_t(lead.tiles_per_span) * lead.R;

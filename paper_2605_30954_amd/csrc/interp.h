@@ -222,6 +222,46 @@ __device__ inline void stage_x_async(float* xs, const float* __restrict__ X, int
   }
 }
 
+// Centred targets of a row tile in binary64 (zero past the last valid row;
+// nvalid >= 1).  Every load reads a clamped valid row unconditionally, so a
+// thread's loads are in flight together instead of one wait per branch.
+__device__ inline void stage_y(double* yts, const float* __restrict__ y, int R, int64_t r0,
+                               int nvalid, double ybar) {
+  constexpr int U = 4;
+  const int bd = blockDim.x;
+  for (int r = threadIdx.x; r < R; r += U * bd) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = y[r0 + min(r + u * bd, nvalid - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ru = r + u * bd;
+      if (ru < R) yts[ru] = ru < nvalid ? double(v[u]) - ybar : 0.0;
+    }
+  }
+}
+
+// Per-individual words (metadata, fit coefficients) fetched one individual
+// ahead, like UopRegs: lane w holds word w, a coalesced vector load.  Reading
+// a word back (v_readlane) waits only for loads issued one individual ago,
+// where a scalar or vector load of the current individual's words, issued
+// after the next program's prefetch, would wait for that prefetch as well.
+struct LaneWords {
+  uint32_t v = 0;
+  // words [0, n0) from a, then [n0, n0 + n1) from b
+  __device__ inline void load(const uint32_t* __restrict__ a, int n0,
+                              const uint32_t* __restrict__ b = nullptr, int n1 = 0) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t* src = lane < n0 ? a + lane : b + (lane - n0);
+    v = lane < n0 + n1 ? *src : 0u;
+  }
+  __device__ inline uint32_t get(int w) const { return __builtin_amdgcn_readlane(v, w); }
+};
+// binary64 from its low and high words
+__device__ inline double words_double(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(uint64_t(hi) << 32 | lo));
+}
+
 // Dynamic work queue of one block and one row tile: every wave claims the
 // next index from an LDS counter (one atomic by lane 0; the value is made
 // wave-uniform with readfirstlane, so loops on it exit with a scalar branch),

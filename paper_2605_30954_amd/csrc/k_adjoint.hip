@@ -370,6 +370,19 @@ struct LaneSink {
   }
 };
 
+// Path tier sink: g * T[e] of this lane's valid rows added into the LDS column
+// of constant e, for e < nc (wave-uniform), expanded over the compile-time
+// entry index so T is read from fixed registers.
+template <int E, int K, int NC>
+__device__ inline void sink_path(LaneSink& sink, const RegTape<K, NC>& T,
+                                 const typename VecT<float, K>::type& g, int nc, int kv) {
+  if constexpr (E < NC) {
+    if (E >= nc) return;
+    sink.template add<typename VecT<float, K>::type, K>(uint32_t(E), g * T.get(E), kv);
+    sink_path<E + 1, K, NC>(sink, T, g, nc, kv);
+  }
+}
+
 // Reverse sweep.  g = adjoint of the program output per row (zero on padding
 // rows); kv = valid rows of this lane.  Uops with no constant below them and
 // no push are skipped with one test.
@@ -444,17 +457,58 @@ __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
 // The compile step lists the flush events in uop order (lane m of `mt` holds
 // event m): each side is lo | n << 7 | assign << 14, a merge's src side in
 // bits 15..29.
+// Chain-rule product f * p in which a factor f of exactly 0 gives 0 whatever
+// p holds.  A local partial of 0 (an operator's protected region, the clamp
+// of exp) ends every derivative path through it; forming the product from the
+// leaves up can first overflow p to infinity (a huge inner partial), and the
+// plain product 0 * inf would be NaN where the derivative is 0.
+template <int K>
+__device__ inline typename VecT<float, K>::type zmul(const typename VecT<float, K>::type& f,
+                                                     const typename VecT<float, K>::type& p) {
+  typename VecT<float, K>::type r;
+#pragma unroll
+  for (int j = 0; j < K; ++j) r[j] = f[j] == 0.0f ? 0.0f : f[j] * p[j];
+  return r;
+}
+
+// T[e] *= f for e in [lo, hi), expanded over the compile-time entry index E
+// (direct register operands, no relative addressing): two uniform compares per
+// entry up to the range's end.
+template <int E, int K, int NC>
+__device__ inline void scale_range(RegTape<K, NC>& T, uint32_t lo, uint32_t hi,
+                                   const typename VecT<float, K>::type& f) {
+  if constexpr (E < NC) {
+    if (uint32_t(E) >= hi) return;
+    if (uint32_t(E) >= lo) {
+      T.put(E, zmul<K>(f, T.get(E)));
+      GG_BRANCH();
+    }
+    scale_range<E + 1, K, NC>(T, lo, hi, f);
+  }
+}
+// T[e] = f for e = lo (no entry when lo >= NC), expanded like scale_range.
+template <int E, int K, int NC>
+__device__ inline void assign_at(RegTape<K, NC>& T, uint32_t lo,
+                                 const typename VecT<float, K>::type& f) {
+  if constexpr (E < NC) {
+    if (uint32_t(E) == lo) {
+      T.put(E, f);
+      GG_BRANCH();
+      return;
+    }
+    assign_at<E + 1, K, NC>(T, lo, f);
+  }
+}
+
 template <int K, int NC>
 __device__ inline void path_flush(RegTape<K, NC>& T, uint32_t side,
                                   const typename VecT<float, K>::type& f) {
   const uint32_t lo = side & 127u, n = (side >> 7) & 127u;
   if (side & (1u << 14)) {
-    if (lo < uint32_t(NC)) T.put(int(lo), f);
+    assign_at<0, K, NC>(T, lo, f);
     GG_BRANCH();
   } else {
-    const uint32_t hi = min(lo + n, uint32_t(NC));
-#pragma unroll 1
-    for (uint32_t e = lo; e < hi; ++e) T.put(int(e), T.get(int(e)) * f);
+    scale_range<0, K, NC>(T, lo, lo + n, f);
     GG_BRANCH();
   }
 }
@@ -516,16 +570,19 @@ __device__ inline typename VecT<float, K>::type run_forward_path(
       GG_BRANCH();
     }
     prefetch_operand<float, K>(nxt.x, xl, rstride, pre);
-    V fa = 1.0f, fs = 1.0f;  // d result / d acc operand, / d src operand
-    if (h & U_CHEAP) {  // ADD 1, SUB 2, RSUB 3, MUL 4
+    if ((h & (U_CHEAP | HDR_ADJ_SRC)) == U_CHEAP) {
+      // ADD 1, SUB 2, RSUB 3, MUL 4 with no constant in the src operand: the
+      // pending factor follows the acc operand (d/d acc is 1, -1 or t).  When
+      // the acc operand holds no constant either, p is dead: it is reset
+      // before it is next read (a constant load, or a src operand that holds
+      // a constant)
       if (h & 4u) {
-        fa = t;
-        fs = acc;
+        p = t * p;
         acc = acc * t;
         GG_BRANCH();
       } else if (h & 2u) {
-        if (h & 1u) { fa = -1.0f; acc = t - acc; GG_BRANCH(); }
-        else { fs = -1.0f; acc = acc - t; GG_BRANCH(); }
+        if (h & 1u) { p = -p; acc = t - acc; GG_BRANCH(); }
+        else { acc = acc - t; GG_BRANCH(); }
         GG_BRANCH();
       } else {
         acc = acc + t;
@@ -533,27 +590,46 @@ __device__ inline typename VecT<float, K>::type run_forward_path(
       }
       GG_BRANCH();
     } else if (h & (HDR_ADJ_ACC | HDR_ADJ_SRC)) {
-      op_partials<K>(uop_op(h), acc, t, fa, fs);
-      GG_BRANCH();
-    } else {
-      op_value<float, K>(uop_op(h), acc, t);
-      GG_BRANCH();
-    }
-    if (h & HDR_ADJ_ACC) {
-      if (h & HDR_ADJ_SRC) {  // merge
-        const uint32_t ev = uint32_t(__builtin_amdgcn_readlane(int(mt), mi));
-        ++mi;
-        path_flush<K, NC>(T, ev & 0x7fffu, fa * p);
-        path_flush<K, NC>(T, ev >> 15, fs);
-        p = 1.0f;
+      V fa = 1.0f, fs = 1.0f;  // d result / d acc operand, / d src operand
+      if (h & U_CHEAP) {
+        if (h & 4u) {
+          fa = t;
+          fs = acc;
+          acc = acc * t;
+          GG_BRANCH();
+        } else if (h & 2u) {
+          if (h & 1u) { fa = -1.0f; acc = t - acc; GG_BRANCH(); }
+          else { fs = -1.0f; acc = acc - t; GG_BRANCH(); }
+          GG_BRANCH();
+        } else {
+          acc = acc + t;
+          GG_BRANCH();
+        }
         GG_BRANCH();
       } else {
-        p = fa * p;
+        op_partials<K>(uop_op(h), acc, t, fa, fs);
+        GG_BRANCH();
+      }
+      if (h & HDR_ADJ_ACC) {
+        if (h & HDR_ADJ_SRC) {  // merge
+          const uint32_t ev = uint32_t(__builtin_amdgcn_readlane(int(mt), mi));
+          ++mi;
+          path_flush<K, NC>(T, ev & 0x7fffu, zmul<K>(fa, p));
+          path_flush<K, NC>(T, ev >> 15, fs);
+          p = 1.0f;
+          GG_BRANCH();
+        } else {
+          p = zmul<K>(fa, p);
+          GG_BRANCH();
+        }
+        GG_BRANCH();
+      } else {
+        p = fs;  // the src operand holds a constant; its pending factor is 1
         GG_BRANCH();
       }
       GG_BRANCH();
-    } else if (h & HDR_ADJ_SRC) {
-      p = fs;  // the src operand's pending factor is 1
+    } else {
+      op_value<float, K>(uop_op(h), acc, t);
       GG_BRANCH();
     }
     cur = nxt;
@@ -585,9 +661,7 @@ template <int W>
 __device__ inline void adj_stage(const AdjParams& p, float* xs, double* yts, int64_t r0, int nvalid,
                                  double ybar) {
   stage_x_async<W>(xs, p.X, p.ldx, p.F, p.R, r0, p.N);
-#pragma unroll 4
-  for (int r = threadIdx.x; r < p.R; r += blockDim.x)
-    yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
+  stage_y(yts, p.y, p.R, r0, nvalid, ybar);
   __builtin_amdgcn_s_waitcnt(0);  // the tile's direct loads have landed
 }
 
@@ -747,11 +821,15 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
   const int GC = p.G * p.C_max;
   const int64_t s_begin = int64_t(it.span) * p.span_rows;
   const int64_t s_end = min<int64_t>(p.N, s_begin + p.span_rows);
+  const uint32_t* meta_w = reinterpret_cast<const uint32_t*>(p.meta);
+  const uint32_t* ab_w = reinterpret_cast<const uint32_t*>(p.ab);
 
   __shared__ int queue;
   for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {  // block-uniform
     const int base = grp * p.G;
     const int Gn = min(p.G, cnt - base);
+    // lane j holds the group's j-th individual (G <= 64)
+    const int lst = lane < Gn ? p.list[base + lane] : 0;
     __syncthreads();  // previous group's partials written
     for (int j = threadIdx.x; j < GC; j += blockDim.x) gacc[j] = 0.0;
     for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
@@ -761,27 +839,29 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
       adj_stage<W>(p, xs, yts, r0, nvalid, ybar);
       __syncthreads();
       const int nbatch = (nvalid + BR - 1) / BR;
-      // the next claimed individual has its program and merge ranges loaded
-      // into registers while this one runs
+      // the next claimed individual has its program, merge ranges, constant
+      // count and fit coefficients loaded into registers while this one runs
       UopRegs<NP> prog, prog_next;
       uint32_t mt = 0, mt_next = 0;
+      LaneWords iw, iw_next;  // n_const, then a and b as four words
       int jj = claim_next(&queue);
       if (jj < Gn) {
-        const int i0 = p.list[base + jj];
+        const int i0 = __builtin_amdgcn_readlane(lst, jj);
         prog.load(p.uops + size_t(i0) * p.U_stride, p.U_stride);
         mt = lane < p.MT ? p.merges[size_t(i0) * p.MT + lane] : 0u;
+        iw.load(meta_w + size_t(i0) * kMetaWords + kMetaNConst, 1, ab_w + size_t(i0) * 4, 4);
       }
       while (jj < Gn) {  // wave-uniform
-        const int i = __builtin_amdgcn_readfirstlane(p.list[base + jj]);
+        const int nc = int(iw.get(0));
+        const double s0m = words_double(iw.get(1), iw.get(2)) - ybar;
+        const double s1 = words_double(iw.get(3), iw.get(4));
         const int jn = claim_next(&queue);
         if (jn < Gn) {
-          const int i1 = p.list[base + jn];
+          const int i1 = __builtin_amdgcn_readlane(lst, jn);
           prog_next.load(p.uops + size_t(i1) * p.U_stride, p.U_stride);
           mt_next = lane < p.MT ? p.merges[size_t(i1) * p.MT + lane] : 0u;
+          iw_next.load(meta_w + size_t(i1) * kMetaWords + kMetaNConst, 1, ab_w + size_t(i1) * 4, 4);
         }
-        const int nc = __builtin_amdgcn_readfirstlane(p.meta[i].n_const);
-        const double s1 = p.ab[size_t(i) * 2 + 1];
-        const double s0m = p.ab[size_t(i) * 2 + 0] - ybar;
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
         for (int b = 0; b < nbatch; ++b) {
           const int lrow = b * BR + lane * K;
@@ -790,15 +870,12 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
           const auto v = run_forward_path<K, D, NC>(prog, mt, xs, R, lrow, T, pf);
           const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid) * pf;
           const int kv = max(0, min(K, nvalid - lrow));
-#pragma unroll
-          for (int j = 0; j < NC; ++j) {
-            if (j >= nc) break;  // wave-uniform
-            sink.template add<typename VecT<float, K>::type, K>(uint32_t(j), g * T.get(j), kv);
-          }
+          sink_path<0, K, NC>(sink, T, g, nc, kv);
         }
         reduce_columns<W>(lacc, nc, lane, gacc + size_t(jj) * p.C_max);
         prog = prog_next;
         mt = mt_next;
+        iw = iw_next;
         jj = jn;
       }
     }

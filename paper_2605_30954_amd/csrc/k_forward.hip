@@ -110,7 +110,12 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   constexpr int BR = 64 * K;  // rows per batch
 
   __shared__ int queue;
+  // status and mu of the group's individuals (G <= 64), read with the queue
+  // claim: one LDS round trip per individual, no global load on the way
+  __shared__ uint2 gmeta[64];
   for (int j = threadIdx.x; j < Gn * 4; j += blockDim.x) accs[j] = 0.0;
+  for (int j = threadIdx.x; j < Gn; j += blockDim.x)
+    gmeta[j] = make_uint2(uint32_t(p.meta[ind0 + j].status), __float_as_uint(p.meta[ind0 + j].mu));
 
   const int64_t span_r0 = int64_t(span) * p.tiles_per_span * R;
   for (int tile = 0; tile < p.tiles_per_span; ++tile) {
@@ -120,9 +125,7 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     __syncthreads();  // previous tile fully consumed
     if (threadIdx.x == 0) queue = 0;
     stage_x_async<W>(xs, p.X, p.ldx, p.F, R, r0, p.N);
-#pragma unroll 4
-    for (int r = threadIdx.x; r < R; r += blockDim.x)
-      yts[r] = r < nvalid ? double(p.y[r0 + r]) - ybar : 0.0;
+    stage_y(yts, p.y, R, r0, nvalid, ybar);
     __builtin_amdgcn_s_waitcnt(0);  // the tile's direct loads have landed
     __syncthreads();
     const int nbatch = (nvalid + BR - 1) / BR;
@@ -133,11 +136,13 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     int jj = claim_next(&queue);
     if (jj < Gn) prog.load(p.uops + size_t(ind0 + jj) * p.U_stride, p.U_stride);
     while (jj < Gn) {
-      const int i = ind0 + jj;
+      const uint2 gm = gmeta[jj];
       const int jn = claim_next(&queue);
+      const int status = __builtin_amdgcn_readfirstlane(int(gm.x));
+      const float mu_f = __uint_as_float(__builtin_amdgcn_readfirstlane(int(gm.y)));
       if (jn < Gn) prog_next.load(p.uops + size_t(ind0 + jn) * p.U_stride, p.U_stride);
-      if (__builtin_amdgcn_readfirstlane(p.meta[i].status) == 0) {
-        const double mu = double(p.meta[i].mu);
+      if (status == 0) {
+        const double mu = double(mu_f);
         const double emu = mu - ybar;
         Moments<SSE> m;
         for (int b = 0; b < nbatch; ++b) {

@@ -36,6 +36,7 @@
 //              when both operands are variables, or the popped slot
 // At most one of {src, load} is a constant, so one payload suffices.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 
 namespace gg {
@@ -156,5 +157,12 @@ struct ProgMeta {
   float mu;         // shift for the moment sums (mean prediction on the first rows)
   int32_t n_merge;  // uops whose two operands both hold constants
 };
+// ProgMeta as 32-bit words, for kernels that fetch it one word per lane
+constexpr int kMetaWords = 8;
+constexpr int kMetaStatus = 1, kMetaNConst = 4, kMetaMu = 6;
+static_assert(sizeof(ProgMeta) == kMetaWords * 4, "ProgMeta is 8 words");
+static_assert(offsetof(ProgMeta, status) == kMetaStatus * 4 && offsetof(ProgMeta, n_const) == kMetaNConst * 4 &&
+                  offsetof(ProgMeta, mu) == kMetaMu * 4,
+              "ProgMeta word offsets");
 
 }  // namespace gg

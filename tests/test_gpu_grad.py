@@ -164,3 +164,28 @@ def test_gradient_every_tier_variant(cid, M, N, tmp_path):
         rep = gate_gradients(grad, st, refs, fl, vy, what=f"cfg{cid} K={K} TC={TC} NC={NC}")
         gated.append(rep["gated"])
     assert min(gated) >= 6
+
+
+def test_clamped_exp_chain_gradient():
+    """exp(exp(c / x0)) * x1 with c / x0 near the clamp of exp: where the inner
+    exp is not clamped, its partial times d(c / x0)/dc (about 5e34 * 8e4)
+    exceeds the binary32 range, while the outer exp is clamped on every row
+    (its partial is 0).  The exact gradient is 0, and it must come out as 0,
+    not NaN, whichever order the chain rule is applied in.  The second program
+    (c halved) reaches the same zero partial without any overflow."""
+    import torch
+    rng = np.random.default_rng(7)
+    N = 4096
+    X = np.stack([rng.uniform(1.2e-5, 1.3e-5, N), rng.standard_normal(N)]).astype(np.float32)
+    y = (2.0 * X[1] + 0.1 * rng.standard_normal(N)).astype(np.float32)
+    ops = np.full((2, 7), -1, np.int8)
+    ops[:] = [32, 64, 3, 8, 8, 65, 2]   # c x0 / exp exp x1 *
+    cs = np.array([[1e-3], [0.5e-3]], np.float32)
+    log(f"[case] clamped exp chain M=2 N={N}")
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    fit, grad, st = gg.grad_consts(t(ops), t(cs), t(X), t(y), return_status=True)
+    fit, grad, st = fit.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0), st
+    assert np.all(np.isfinite(fit)), fit
+    assert np.array_equal(grad, np.zeros_like(grad)), grad
