@@ -100,7 +100,7 @@ Layout layout_of(const Shape& s) {
   o = align256(o + 64);
   l.gpart = o;
   o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
-  l.adjl = o;  // adjoint tier lists [4][M] + counts [4] + path redo flags [M] at 5M, or
+  l.adjl = o;  // adjoint tier lists [4][M], counts [4], then the path redo flags [M], or
                // per-individual counts [M][4] + a list
   o = align256(o + size_t(s.M) * 8 * sizeof(int32_t) + 64);
   l.redo_span = o;  // path tier fallback: [M][n_spans] bytes
@@ -471,7 +471,7 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     int* lists = reinterpret_cast<int*>(c.ws + l.adjl);
     int* counts = lists + 4 * size_t(c.s.M);
     const size_t M = size_t(c.s.M);
-    int* redo = lists + 5 * M;
+    int* redo = counts + 4;  // path fallback flags [M], right after the four counts
     uint8_t* redo_span = reinterpret_cast<uint8_t*>(c.ws + l.redo_span);
     int* rd = ac.nc_p > 0 ? redo : nullptr;  // the tape tiers' fallback flags
     uint8_t* rs = ac.nc_p > 0 ? redo_span : nullptr;

@@ -34,6 +34,21 @@ struct VecT {
   typedef T type __attribute__((ext_vector_type(K)));
 };
 
+// Rows of a batch.  A batch covers 64*K consecutive rows of the tile.  For
+// K >= 4, lane l holds rows 4l + 256q + {0, 1, 2, 3} for q < K/4: each float4
+// LDS read takes a 16-byte run per lane with consecutive lanes on consecutive
+// runs (no bank conflict), where K consecutive rows per lane would put lanes
+// l and l + 8 on the same banks.  For K < 4, lane l holds rows lK + j.
+// Element j of a lane is row lane_row(l) + row_off(j) of the batch.
+template <int K>
+__host__ __device__ constexpr int lane_row(int lane) {
+  return K >= 4 ? 4 * lane : K * lane;
+}
+template <int K>
+__host__ __device__ constexpr int row_off(int j) {
+  return K >= 4 ? (j >> 2) * 256 + (j & 3) : j;
+}
+
 template <typename T, int K>
 __device__ inline typename VecT<T, K>::type lds_rows(const float* __restrict__ p) {
   typename VecT<T, K>::type v;
@@ -41,7 +56,7 @@ __device__ inline typename VecT<T, K>::type lds_rows(const float* __restrict__ p
   if constexpr (K >= 4) {
 #pragma unroll
     for (int j = 0; j < K; j += 4) {
-      const float4 q = *reinterpret_cast<const float4*>(p + j);
+      const float4 q = *reinterpret_cast<const float4*>(p + row_off<K>(j));
       v[j] = T(q.x);
       v[j + 1] = T(q.y);
       v[j + 2] = T(q.z);
@@ -382,7 +397,7 @@ __device__ inline void op_value(uint32_t op, typename VecT<T, K>::type& acc,
 // Evaluate the program on K rows per lane; returns the predictions.
 //   prog    uop source of this individual (UopMem or UopRegs)
 //   xt      LDS row tile: feature k, row r at xt[k*rstride + r]
-//   lrow    this lane's first row within the tile (multiple of K)
+//   lrow    this lane's first row within the tile (batch start + lane_row)
 //
 // The scalar unit is shared by the four SIMDs of a compute unit and its
 // instructions (field tests, branches) bound the interpreter's rate, so every

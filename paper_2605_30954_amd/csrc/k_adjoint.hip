@@ -332,14 +332,15 @@ __device__ inline typename VecT<float, K>::type run_forward_taped(
   return acc;
 }
 
-// Sum over the wave of this lane's first `kv` values (padding rows excluded:
-// their adjoints may be NaN after multiplying a zero by an infinite partial),
-// in binary64.
+// Sum over the wave of this lane's values on valid rows, in binary64.  kv is
+// the number of the tile's valid rows from the lane's first row on, so element
+// j is valid iff row_off(j) < kv (padding rows are excluded: their adjoints may
+// be NaN after multiplying a zero by an infinite partial).
 template <int K>
 __device__ inline double wave_total(const typename VecT<float, K>::type& v, int kv) {
   double s = 0.0;
 #pragma unroll
-  for (int j = 0; j < K; ++j) s += j < kv ? double(v[j]) : 0.0;
+  for (int j = 0; j < K; ++j) s += row_off<K>(j) < kv ? double(v[j]) : 0.0;
   return wave_sum(s);
 }
 
@@ -363,7 +364,7 @@ struct LaneSink {
   __device__ inline void add(uint32_t c, const V& v, int kv) {
     float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < K; ++j) s += j < kv ? v[j] : 0.0f;
+    for (int j = 0; j < K; ++j) s += row_off<K>(j) < kv ? v[j] : 0.0f;
     // read-modify-write inside the LDS unit (ds_add_f32, no return value, so
     // nothing waits on it); only this lane writes this word, in program order
     (void)atomicAdd(&col[c * kColStride], s);
@@ -384,7 +385,8 @@ __device__ inline void sink_path(LaneSink& sink, const RegTape<K, NC>& T,
 }
 
 // Reverse sweep.  g = adjoint of the program output per row (zero on padding
-// rows); kv = valid rows of this lane.  Uops with no constant below them and
+// rows); kv = valid rows of the tile from this lane's first row on (element j
+// is valid iff row_off(j) < kv).  Uops with no constant below them and
 // no push are skipped with one test.
 template <int K, int D, class Src, class Tape, class Sink>
 __device__ inline void run_reverse(const Src& prog, int n_uops, int n_tape,
@@ -674,8 +676,8 @@ __device__ inline typename VecT<float, K>::type adj_seed(const typename VecT<flo
   typename VecT<float, K>::type g;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const bool ok = lrow + j < nvalid;
-    const double res = (s0m + s1 * double(v[j])) - yts[lrow + j];
+    const bool ok = lrow + row_off<K>(j) < nvalid;
+    const double res = (s0m + s1 * double(v[j])) - yts[lrow + row_off<K>(j)];
     g[j] = ok ? float(res) : 0.0f;
   }
   return g;
@@ -774,11 +776,11 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
         const int nb = keep_path_span(p, i, it.span) ? 0 : nbatch;
         for (int b = SPLIT ? wv : 0; b < nb; b += SPLIT ? W : 1) {
-          const int lrow = b * BR + lane * K;
+          const int lrow = b * BR + lane_row<K>(lane);
           RegTape<K, TC> tape;
           const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
           const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-          const int kv = max(0, min(K, nvalid - lrow));
+          const int kv = nvalid - lrow;
           run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
         }
         reduce_columns<W>(lacc, nc, lane, gmine + size_t(jj) * p.C_max);
@@ -864,12 +866,12 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
         }
         for (int c = 0; c < nc; ++c) lacc[c * kColStride + lane] = 0.0f;
         for (int b = 0; b < nbatch; ++b) {
-          const int lrow = b * BR + lane * K;
+          const int lrow = b * BR + lane_row<K>(lane);
           RegTape<K, NC> T;
           typename VecT<float, K>::type pf;
           const auto v = run_forward_path<K, D, NC>(prog, mt, xs, R, lrow, T, pf);
           const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid) * pf;
-          const int kv = max(0, min(K, nvalid - lrow));
+          const int kv = nvalid - lrow;
           sink_path<0, K, NC>(sink, T, g, nc, kv);
         }
         reduce_columns<W>(lacc, nc, lane, gacc + size_t(jj) * p.C_max);
@@ -942,10 +944,10 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
         const UopMem prog{p.uops + size_t(i) * p.U_stride};
         WaveSink sink{gacc + size_t(wv) * GC + size_t(jj) * p.C_max};
         for (int b = wv; b < nbatch; b += W) {
-          const int lrow = b * BR + lane * K;
+          const int lrow = b * BR + lane_row<K>(lane);
           const auto v = run_forward_taped<K, D>(prog, xs, R, lrow, tape);
           const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid);
-          const int kv = max(0, min(K, nvalid - lrow));
+          const int kv = nvalid - lrow;
           run_reverse<K, D>(prog, pm.n_uops, pm.n_tape, g, tape, sink, kv);
         }
       }

@@ -60,15 +60,15 @@ template <typename T, int K, bool SSE>
 __device__ inline void accumulate(Moments<SSE>& m, const typename VecT<T, K>::type& p,
                                   const double* __restrict__ yt, int lrow, int nvalid, double mu,
                                   double emu) {
-  if (lrow + K <= nvalid) {
+  if (lrow + row_off<K>(K - 1) < nvalid) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) m.add(double(p[j]) - mu, yt[lrow + j], emu);
+    for (int j = 0; j < K; ++j) m.add(double(p[j]) - mu, yt[lrow + row_off<K>(j)], emu);
   } else {
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const bool v = lrow + j < nvalid;
+      const bool v = lrow + row_off<K>(j) < nvalid;
       const double d = double(p[j]) - mu;
-      m.add(v ? d : 0.0, v ? yt[lrow + j] : 0.0, v ? emu : 0.0);
+      m.add(v ? d : 0.0, v ? yt[lrow + row_off<K>(j)] : 0.0, v ? emu : 0.0);
     }
   }
 }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
         const double emu = mu - ybar;
         Moments<SSE> m;
         for (int b = 0; b < nbatch; ++b) {
-          const int lrow = b * BR + lane * K;
+          const int lrow = b * BR + lane_row<K>(lane);
           const auto v = run_program<T, K, D>(prog, xs, R, lrow);
           accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
         }
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(W * 64) void k_plain_fwd(PlainParams p) {
       __syncthreads();
       const int nbatch = (nvalid + BR - 1) / BR;
       for (int b = w; b < nbatch; b += W) {
-        const int lrow = b * BR + lane * K;
+        const int lrow = b * BR + lane_row<K>(lane);
         const auto v = run_program<T, K, D>(UopMem{p.prog}, xs, R, lrow);
         accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
       }

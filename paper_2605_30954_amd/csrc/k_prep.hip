@@ -478,11 +478,11 @@ __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, i
   if (i >= M) return;
   if (meta[i].status != 0) return;
   const uint2* prog = uops + size_t(i) * U_stride;
-  const auto p = run_program<T, K, D>(UopMem{prog}, xs, R, lane * K);
+  const auto p = run_program<T, K, D>(UopMem{prog}, xs, R, lane_row<K>(lane));
   float s = 0.0f;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const bool v = lane * K + j < nval;
+    const bool v = lane_row<K>(lane) + row_off<K>(j) < nval;
     s += v ? float(p[j]) : 0.0f;
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);

@@ -51,6 +51,13 @@ def test_cfg2_gradients():
     run_grad(2, 64, 10007)
 
 
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_gradients_tiny_batches(M):
+    """Batches of fewer than four programs (the tier counts and the path
+    tier's fallback flags share one workspace region)."""
+    run_grad(4, M, 5000, salt=2, min_gated=0)
+
+
 def test_cfg5_gradients_full_operator_set():
     # most random height-7 programs over all 11 operators have gradients that a
     # one-ulp perturbation of the node values moves by more than the gate: they
