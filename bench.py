@@ -35,7 +35,7 @@ SYM_NAME = {0: "add", 1: "sub", 2: "mul", 3: "div", 4: "sin", 5: "cos", 6: "sq",
 ADJ_SOURCES = ["paper_2605_30954_amd/csrc/k_adjoint.hip", "paper_2605_30954_amd/csrc/interp.h",
                "paper_2605_30954_amd/csrc/devmath.h", "paper_2605_30954_amd/csrc/uop.h",
                "paper_2605_30954_amd/csrc/kernels.h", "paper_2605_30954_amd/build.py"]
-ADJ_KERNELS = ("k_adj_partition", "k_adj_path", "k_adj_relist", "k_adj_reg", "k_adj_lds")
+ADJ_KERNELS = ("k_adj_partition", "k_adj_path", "k_adj_reg", "k_adj_lds")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_cfg2_traffic.json")
 
 
@@ -190,7 +190,7 @@ def roofline(gg, ops, cfg, N, stream, step, steps, fit_aux):
     launches = {k: v[0] / steps for k, v in rep.items()}
     # the adjoint's tier kernels split the individuals between them (after a
     # partition kernel that lists each tier): together they are one launch
-    adj_parts = ("adjoint_partition", "adjoint_path", "adjoint_relist", "adjoint_reg", "adjoint_reg_b",
+    adj_parts = ("adjoint_partition", "adjoint_path", "adjoint_reg", "adjoint_reg_b",
                  "adjoint_lds")
     adj_ms = sum(per.get(k, 0.0) for k in adj_parts)
     cand = {"fused_forward": per.get("fused_forward", 0.0), "adjoint": adj_ms}

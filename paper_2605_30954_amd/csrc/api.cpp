@@ -479,9 +479,8 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     if (ac.nc_p > 0) {
       GG_HIP(launch_fill_u32(reinterpret_cast<unsigned*>(redo), c.s.M, 0u, c.stream));
       GG_TIMED("adjoint_path", launch_adjoint_path(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                   gpart, merges, l.MT, redo, redo_span, lists + 3 * M,
-                                                   counts + 3, c.stream));
-      GG_TIMED("adjoint_relist", launch_adjoint_relist(ac, meta, c.s.M, redo, lists, counts, c.stream));
+                                                   gpart, merges, l.MT, redo, redo_span, lists, counts,
+                                                   c.stream));
     }
     if (ac.need_a)
       GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,

@@ -60,6 +60,9 @@ struct AdjParams {
   int* redo;               // [M] path tier: set when an individual's partials are not finite
   uint8_t* redo_span;      // [M][n_spans] ... and for which spans; the tape tiers then
                            // redo only those spans of a flagged individual
+  int* fb_lists;           // path tier: the tier lists [4][M] and counts [4], to which
+  int* fb_counts;          // a flagged individual is appended (tier B, or C)
+  int tc_b;                // tier B's tape entries
 };
 
 // A tape tier skips span s of individual i when i fell back from the path
@@ -885,13 +888,21 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
     adj_write<false>(p, it.span, base, Gn, gacc);
     // a partial that is not finite may be an overflow of an intermediate
     // product that the reverse sweep does not form: that span of the
-    // individual is differentiated again by the tape tiers
+    // individual is differentiated again by the tape tiers.  The first span
+    // of an individual to fall back appends it to tier B's list (tier C's for
+    // a longer tape or more constants); the tape tiers' results do not depend
+    // on the order of their lists.
     for (int jj = threadIdx.x; jj < Gn; jj += blockDim.x) {
       bool bad = false;
       for (int c = 0; c < p.C_max; ++c) bad = bad || !isfinite(gacc[size_t(jj) * p.C_max + c]);
       const int i = p.list[base + jj];
       p.redo_span[size_t(i) * p.n_spans + it.span] = bad ? 1 : 0;
-      if (bad) p.redo[i] = 1;
+      if (bad && atomicExch(&p.redo[i], 1) == 0) {
+        const ProgMeta& pm = p.meta[i];
+        const int tier = (pm.n_const <= p.lane_consts && pm.n_tape <= p.tc_b) ? 1 : 2;
+        const int slot = atomicAdd(&p.fb_counts[tier], 1);
+        p.fb_lists[size_t(tier) * p.M + slot] = i;
+      }
     }
   }
 }
@@ -1027,76 +1038,18 @@ static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, co
                             const DataArgs& d, const double* stats, const double* ab,
                             double* gpart, const int* list, const int* count,
                             const uint32_t* merges = nullptr, int MT = 0, int* redo = nullptr,
-                            uint8_t* redo_span = nullptr) {
+                            uint8_t* redo_span = nullptr, int* fb_lists = nullptr,
+                            int* fb_counts = nullptr) {
   return AdjParams{uops, U_stride, meta, M, C_max, d.X, d.ldx, d.F, d.N, d.y, stats, ab, gpart,
                    list, count, c.R, c.G, n_groups, a.n_spans, a.span_rows, a.tape_cap,
-                   a.lane_consts, merges, MT, redo, redo_span};
+                   a.lane_consts, merges, MT, redo, redo_span, fb_lists, fb_counts,
+                   a.need_b ? a.tc_b : a.tc_a};
 }
 
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                     int* lists, int* counts, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_partition, dim3(1), dim3(kPartThreads), 0, s, meta, ab, M, a.tc_a,
                      a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.nc_p, lists, counts);
-  return hipGetLastError();
-}
-
-// Path tier fallback: the individuals flagged in redo[] (few) are appended,
-// in batch order, to the list of tape tier B (tape of at most tcB entries and
-// at most CC constants; its waves share each individual, so a lone one still
-// keeps a block busy) or else tier C.  One block; a block-wide scan keeps the
-// order deterministic.
-__global__ __launch_bounds__(kPartThreads) void k_adj_relist(const ProgMeta* __restrict__ meta, int M,
-                                                             int tcB, int CC,
-                                                             const int* __restrict__ redo,
-                                                             int* __restrict__ lists,
-                                                             int* __restrict__ counts) {
-  __shared__ int sc[2][kPartThreads];
-  __shared__ int base[2];
-  const int t = threadIdx.x;
-  const int chunk = (M + kPartThreads - 1) / kPartThreads;
-  const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
-  auto tier_of = [&](int i) {
-    const ProgMeta& pm = meta[i];
-    return (pm.n_const <= CC && pm.n_tape <= tcB) ? 0 : 1;
-  };
-  int n[2] = {0, 0};
-  for (int i = lo; i < hi; ++i)
-    if (redo[i]) ++n[tier_of(i)];
-  sc[0][t] = n[0];
-  sc[1][t] = n[1];
-  if (t == 0) {
-    base[0] = counts[1];
-    base[1] = counts[2];
-  }
-  __syncthreads();
-  for (int o = 1; o < kPartThreads; o <<= 1) {  // inclusive Hillis-Steele scan
-    int a0 = 0, a1 = 0;
-    if (t >= o) {
-      a0 = sc[0][t - o];
-      a1 = sc[1][t - o];
-    }
-    __syncthreads();
-    sc[0][t] += a0;
-    sc[1][t] += a1;
-    __syncthreads();
-  }
-  int w0 = base[0] + sc[0][t] - n[0], w1 = base[1] + sc[1][t] - n[1];
-  for (int i = lo; i < hi; ++i) {
-    if (!redo[i]) continue;
-    if (tier_of(i) == 0) lists[size_t(M) + w0++] = i;
-    else lists[size_t(2) * M + w1++] = i;
-  }
-  __syncthreads();
-  if (t == kPartThreads - 1) {
-    counts[1] = base[0] + sc[0][t];
-    counts[2] = base[1] + sc[1][t];
-  }
-}
-
-hipError_t launch_adjoint_relist(const AdjPlan& a, const ProgMeta* meta, int M, const int* redo,
-                                 int* lists, int* counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_relist, dim3(1), dim3(kPartThreads), 0, s, meta, M, a.tc_b,
-                     a.lane_consts, redo, lists, counts);
   return hipGetLastError();
 }
 
@@ -1147,10 +1100,11 @@ hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride
                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                                const double* stats, const double* ab, double* gpart,
                                const uint32_t* merges, int MT, int* redo, uint8_t* redo_span,
-                               const int* list, const int* count, hipStream_t s) {
+                               int* lists, int* counts, hipStream_t s) {
   const TileCfg& c = a.path;
   const AdjParams ap = adj_params(a, c, c.n_groups, uops, U_stride, meta, M, C_max, d, stats, ab,
-                                  gpart, list, count, merges, MT, redo, redo_span);
+                                  gpart, lists + size_t(kTierPath) * M, counts + kTierPath, merges, MT,
+                                  redo, redo_span, lists, counts);
   if (c.W != 4 || MT < 1 || !redo || !redo_span) return hipErrorInvalidValue;
   if (c.K == 4 && a.nc_p == 16 && c.D == 4) return path_impl<4, 4, 4, 16>(c, ap, s);
   if (c.K == 4 && a.nc_p == 16 && c.D == 8) return path_impl<4, 8, 4, 16>(c, ap, s);

@@ -103,17 +103,15 @@ hipError_t launch_adjoint_reg(const AdjPlan& a, int tier, const uint2* uops, int
                               const double* stats, const double* ab, double* gpart,
                               const int* list, const int* count, int* redo,
                               uint8_t* redo_span, hipStream_t s);
-// path tier; redo[i] is set for an individual with a partial that is not
-// finite (zero redo[] before) and redo_span[i][s] says which spans (written
-// for every span of every individual of the tier)
+// path tier over lists[3][0 .. counts[3]); redo[i] is set for an individual
+// with a partial that is not finite (zero redo[] before), redo_span[i][s] says
+// which spans (written for every span of every individual of the tier), and
+// the individual is appended to the list of tier B (or C) with its count
 hipError_t launch_adjoint_path(const AdjPlan& a, const uint2* uops, int U_stride,
                                const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                                const double* stats, const double* ab, double* gpart,
                                const uint32_t* merges, int MT, int* redo, uint8_t* redo_span,
-                               const int* list, const int* count, hipStream_t s);
-// appends the individuals flagged in redo[] to the lists of tiers B and C
-hipError_t launch_adjoint_relist(const AdjPlan& a, const ProgMeta* meta, int M, const int* redo,
-                                 int* lists, int* counts, hipStream_t s);
+                               int* lists, int* counts, hipStream_t s);
 hipError_t launch_adjoint_lds(const AdjPlan& a, const uint2* uops, int U_stride,
                               const ProgMeta* meta, int M, int C_max, const DataArgs& d,
                               const double* stats, const double* ab, double* gpart,
