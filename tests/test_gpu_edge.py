@@ -57,6 +57,36 @@ def test_ragged_row_counts(N):
             assert abs(f[i].item() - r["fitness"]) <= 1e-5 * abs(r["fitness"]) + 1e-10 * vy + 1e-30, (N, i)
 
 
+@pytest.mark.parametrize("N", [1, 2, 63, 65, 257, 513, 2049])
+def test_ragged_row_counts_gradients(N):
+    """Constant gradients at tiny and ragged row counts (rows past the last
+    one are masked in the forward and in every adjoint sink), against the
+    oracle's forward-mode gradient; error bound relative to gabs, the sum of
+    the per-row terms' magnitudes, plus 1e-12 absolute (targets are O(1): two
+    rows are fitted exactly, so the residuals are rounding alone)."""
+    from oracle import grad as OG
+    log(f"[case] ragged gradient N={N}")
+    rng = np.random.default_rng(100 + N)
+    X = rng.uniform(-2, 2, (3, N)).astype(np.float32)
+    y = (X[0] * X[1] - np.cos(X[2])).astype(np.float32)
+    progs = [([V[0], C, O.ADD, O.SIN], [0.3]),                   # sin(x0 + c)
+             ([C, V[1], O.MUL, V[2], O.COS, O.ADD], [1.7]),       # c x1 + cos x2
+             ([V[0], C, O.MUL, O.EXP, V[1], C, O.SUB, O.MUL], [0.4, 0.9]),
+             ([V[0], V[1], O.MUL, C, O.DIV, V[2], C, O.ADD, O.SQ, O.ADD], [1.3, -0.2])]
+    ops, cs = programs(progs)
+    f, g, st = gg.grad_consts(*dev(ops, cs, X, y), return_status=True)
+    f, g, st = f.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+    for i in range(len(progs)):
+        genes, gc = OC.decode_one(ops[i], cs[i], 6)
+        s, gr = OG.gradient(genes, gc, 6, X, y, linear_scaling=True, rng="f32")
+        assert st[i] == s["status"], (N, i)
+        nc = len(gr)
+        assert np.all(g[i, nc:] == 0.0)
+        for j in range(nc):
+            tol = 1e-5 * s["gabs"][j] + 1e-6 * abs(gr[j]) + 1e-12
+            assert abs(g[i, j] - gr[j]) <= tol, (N, i, j, g[i, j], gr[j], s["gabs"][j])
+
+
 def test_single_individual_and_lone_terminals():
     rng = np.random.default_rng(5)
     X = rng.normal(size=(2, 3000)).astype(np.float32)
