@@ -267,8 +267,9 @@ struct LaneWords {
   __device__ inline void load(const uint32_t* __restrict__ a, int n0,
                               const uint32_t* __restrict__ b = nullptr, int n1 = 0) {
     const int lane = threadIdx.x & 63;
-    const uint32_t* src = lane < n0 ? a + lane : b + (lane - n0);
-    v = lane < n0 + n1 ? *src : 0u;
+    v = 0u;
+    if (lane < n0) v = a[lane];
+    else if (lane < n0 + n1) v = b[lane - n0];
   }
   __device__ inline uint32_t get(int w) const { return __builtin_amdgcn_readlane(v, w); }
 };

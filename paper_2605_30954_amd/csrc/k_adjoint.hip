@@ -169,7 +169,8 @@ struct LdsTape {
 // vector register tuple holds at most 32 floats, and only a vector that fits
 // one tuple is addressed in registers).  The entry index is wave-uniform (it
 // follows the uop stream), so the compiler reads and writes the tuples with
-// s_set_gpr_idx moves instead of scratch memory.
+// s_set_gpr_idx moves instead of scratch memory.  The path tier's array T is
+// a RegTape indexed only by compile-time entries (fixed registers).
 template <int K, int TC>
 struct RegTape {
   static_assert(TC <= 32, "a tape row must fit one VGPR tuple");
