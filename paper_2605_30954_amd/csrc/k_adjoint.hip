@@ -364,11 +364,12 @@ struct WaveSink {
 };
 struct LaneSink {
   float* col;
-  template <class V, int K>
+  // FULL: every row of the batch is valid (no per-element test)
+  template <class V, int K, bool FULL = false>
   __device__ inline void add(uint32_t c, const V& v, int kv) {
     float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < K; ++j) s += row_off<K>(j) < kv ? v[j] : 0.0f;
+    for (int j = 0; j < K; ++j) s += (FULL || row_off<K>(j) < kv) ? v[j] : 0.0f;
     // read-modify-write inside the LDS unit (ds_add_f32, no return value, so
     // nothing waits on it); only this lane writes this word, in program order
     (void)atomicAdd(&col[c * kColStride], s);
@@ -378,13 +379,13 @@ struct LaneSink {
 // Path tier sink: g * T[e] of this lane's valid rows added into the LDS column
 // of constant e, for e < nc (wave-uniform), expanded over the compile-time
 // entry index so T is read from fixed registers.
-template <int E, int K, int NC>
+template <int E, int K, int NC, bool FULL>
 __device__ inline void sink_path(LaneSink& sink, const RegTape<K, NC>& T,
                                  const typename VecT<float, K>::type& g, int nc, int kv) {
   if constexpr (E < NC) {
     if (E >= nc) return;
-    sink.template add<typename VecT<float, K>::type, K>(uint32_t(E), g * T.get(E), kv);
-    sink_path<E + 1, K, NC>(sink, T, g, nc, kv);
+    sink.template add<typename VecT<float, K>::type, K, FULL>(uint32_t(E), g * T.get(E), kv);
+    sink_path<E + 1, K, NC, FULL>(sink, T, g, nc, kv);
   }
 }
 
@@ -672,15 +673,15 @@ __device__ inline void adj_stage(const AdjParams& p, float* xs, double* yts, int
 }
 
 // Per-row output adjoint: the residual (s0 - ybar) + s1 p - (y - ybar) in
-// binary64, zero on padding rows.
-template <int K>
+// binary64, zero on padding rows (FULL: the batch has none).
+template <int K, bool FULL = false>
 __device__ inline typename VecT<float, K>::type adj_seed(const typename VecT<float, K>::type& v,
                                                          double s0m, double s1,
                                                          const double* yts, int lrow, int nvalid) {
   typename VecT<float, K>::type g;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const bool ok = lrow + row_off<K>(j) < nvalid;
+    const bool ok = FULL || lrow + row_off<K>(j) < nvalid;
     const double res = (s0m + s1 * double(v[j])) - yts[lrow + row_off<K>(j)];
     g[j] = ok ? float(res) : 0.0f;
   }
@@ -874,9 +875,14 @@ __global__ __launch_bounds__(W * 64) void k_adj_path(AdjParams p) {
           RegTape<K, NC> T;
           typename VecT<float, K>::type pf;
           const auto v = run_forward_path<K, D, NC>(prog, mt, xs, R, lrow, T, pf);
-          const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid) * pf;
           const int kv = nvalid - lrow;
-          sink_path<0, K, NC>(sink, T, g, nc, kv);
+          if ((b + 1) * BR <= nvalid) {  // a full batch (wave-uniform): no row tests
+            const auto g = adj_seed<K, true>(v, s0m, s1, yts, lrow, nvalid) * pf;
+            sink_path<0, K, NC, true>(sink, T, g, nc, kv);
+          } else {
+            const auto g = adj_seed<K>(v, s0m, s1, yts, lrow, nvalid) * pf;
+            sink_path<0, K, NC, false>(sink, T, g, nc, kv);
+          }
         }
         reduce_columns<W>(lacc, nc, lane, gacc + size_t(jj) * p.C_max);
         prog = prog_next;
