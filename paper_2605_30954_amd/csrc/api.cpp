@@ -475,9 +475,8 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     uint8_t* redo_span = reinterpret_cast<uint8_t*>(c.ws + l.redo_span);
     int* rd = ac.nc_p > 0 ? redo : nullptr;  // the tape tiers' fallback flags
     uint8_t* rs = ac.nc_p > 0 ? redo_span : nullptr;
-    GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, c.stream));
+    GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, rd, c.stream));
     if (ac.nc_p > 0) {
-      GG_HIP(launch_fill_u32(reinterpret_cast<unsigned*>(redo), c.s.M, 0u, c.stream));
       GG_TIMED("adjoint_path", launch_adjoint_path(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
                                                    gpart, merges, l.MT, redo, redo_span, lists, counts,
                                                    c.stream));

@@ -90,13 +90,14 @@ __device__ inline int adj_tier(const ProgMeta& pm, double s1, int tcA, int tcB, 
 constexpr int kPartThreads = 1024;
 __global__ __launch_bounds__(kPartThreads) void k_adj_partition(
     const ProgMeta* __restrict__ meta, const double* __restrict__ ab, int M, int tcA, int tcB,
-    int CC, int ncP, int* __restrict__ lists, int* __restrict__ counts) {
+    int CC, int ncP, int* __restrict__ lists, int* __restrict__ counts, int* __restrict__ redo) {
   __shared__ int sc[kTiers][kPartThreads];
   const int t = threadIdx.x;
   const int chunk = (M + kPartThreads - 1) / kPartThreads;
   const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
   int n[kTiers] = {0, 0, 0, 0};
   for (int i = lo; i < hi; ++i) {
+    if (redo) redo[i] = 0;  // the path tier's fallback flags start clear
     const int k = adj_tier(meta[i], ab[size_t(i) * 2 + 1], tcA, tcB, CC, ncP);
 #pragma unroll
     for (int q = 0; q < kTiers; ++q) n[q] += k == q;
@@ -1054,9 +1055,9 @@ static AdjParams adj_params(const AdjPlan& a, const TileCfg& c, int n_groups, co
 }
 
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
-                                    int* lists, int* counts, hipStream_t s) {
+                                    int* lists, int* counts, int* redo, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_partition, dim3(1), dim3(kPartThreads), 0, s, meta, ab, M, a.tc_a,
-                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.nc_p, lists, counts);
+                     a.need_b ? a.tc_b : a.tc_a, a.lane_consts, a.nc_p, lists, counts, redo);
   return hipGetLastError();
 }
 

@@ -89,9 +89,9 @@ struct AdjPlan {
 };
 
 // Tier lists: lists[tier * M + k], counts[tier], tier = 0 A, 1 B, 2 C, 3 path
-// (after finalize).
+// (after finalize); redo[M] (the path tier's fallback flags, or null) cleared.
 hipError_t launch_adjoint_partition(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
-                                    int* lists, int* counts, hipStream_t s);
+                                    int* lists, int* counts, int* redo, hipStream_t s);
 // Plain form: counts[4i + tier] = 1 for individual i's tier, list0[0] = 0.
 hipError_t launch_adjoint_tier_flags(const AdjPlan& a, const ProgMeta* meta, const double* ab, int M,
                                      int* counts, int* list0, hipStream_t s);
