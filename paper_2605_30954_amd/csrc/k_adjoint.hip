@@ -71,6 +71,17 @@ __device__ inline bool keep_path_span(const AdjParams& p, int i, int span) {
   return p.redo != nullptr && p.redo[i] != 0 && p.redo_span[size_t(i) * p.n_spans + span] == 0;
 }
 
+// A tape tier has nothing to do on span s for a group whose individuals all
+// keep the path tier's partials of s (the fallback tier holds only fallen-back
+// individuals, flagged on few spans): the block skips the span, staging
+// included.  Block-uniform (global data only).
+__device__ inline bool group_keeps_span(const AdjParams& p, int base, int Gn, int span) {
+  if (p.redo == nullptr) return false;
+  for (int jj = 0; jj < Gn; ++jj)
+    if (!keep_path_span(p, p.list[base + jj], span)) return false;
+  return true;
+}
+
 // Tier of an individual: -1 no gradient work (bad program, non-finite, b = 0
 // or no constant), 3 path forward mode (at most ncP constants), 0 register
 // tape A, 1 register tape B, 2 LDS tape.
@@ -756,6 +767,7 @@ __global__ __launch_bounds__(W * 64) void k_adj_reg(AdjParams p) {
   for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {  // block-uniform
     const int base = grp * p.G;
     const int Gn = min(p.G, cnt - base);
+    if (group_keeps_span(p, base, Gn, it.span)) continue;
     __syncthreads();  // previous group's partials written
     for (int j = threadIdx.x; j < COPIES * GC; j += blockDim.x) gacc[j] = 0.0;
     for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
@@ -945,6 +957,7 @@ __global__ __launch_bounds__(W * 64) void k_adj_lds(AdjParams p) {
   for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {
     const int base = grp * p.G;
     const int Gn = min(p.G, cnt - base);
+    if (group_keeps_span(p, base, Gn, it.span)) continue;
     __syncthreads();
     for (int j = threadIdx.x; j < W * GC; j += blockDim.x) gacc[j] = 0.0;
     for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
