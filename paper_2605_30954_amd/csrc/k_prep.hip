@@ -460,7 +460,9 @@ hipError_t launch_compile(const int8_t* ops, int M, int L_max, const float* cons
 
 // -------------------------------------------------------------------- probe
 // One wave per individual; the block stages the first 64*K rows of X in LDS.
-template <typename T, int K, int D>
+// The program is read into registers with one coalesced load (NP register
+// pairs), so the uop stream costs no memory round trip per uop.
+template <typename T, int K, int D, int NP>
 __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, int U_stride,
                                                ProgMeta* __restrict__ meta, int M,
                                                const float* __restrict__ X, int64_t ldx, int F,
@@ -477,8 +479,9 @@ __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, i
   const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
   if (i >= M) return;
   if (meta[i].status != 0) return;
-  const uint2* prog = uops + size_t(i) * U_stride;
-  const auto p = run_program<T, K, D>(UopMem{prog}, xs, R, lane_row<K>(lane));
+  UopRegs<NP> prog;
+  prog.load(uops + size_t(i) * U_stride, U_stride);
+  const auto p = run_program<T, K, D>(prog, xs, R, lane_row<K>(lane));
   float s = 0.0f;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -490,21 +493,34 @@ __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, i
   if (lane == 0) meta[i].mu = isfinite(mu) ? mu : 0.0f;
 }
 
-template <typename T, int K, int D>
+template <typename T, int K, int D, int NP>
 static hipError_t probe_impl(const uint2* uops, int U_stride, ProgMeta* meta, int M,
                              const DataArgs& d, hipStream_t s) {
   const size_t sh = size_t(d.F) * 64 * K * sizeof(float);
-  hipLaunchKernelGGL((k_probe<T, K, D>), dim3((M + 3) / 4), dim3(256), sh, s, uops, U_stride, meta,
-                     M, d.X, d.ldx, d.F, d.N);
+  hipLaunchKernelGGL((k_probe<T, K, D, NP>), dim3((M + 3) / 4), dim3(256), sh, s, uops, U_stride,
+                     meta, M, d.X, d.ldx, d.F, d.N);
   return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t probe_np(int NP, const uint2* uops, int U_stride, ProgMeta* meta, int M,
+                           const DataArgs& d, hipStream_t s) {
+  switch (NP) {
+    case 1: return probe_impl<T, 4, D, 1>(uops, U_stride, meta, M, d, s);
+    case 2: return probe_impl<T, 4, D, 2>(uops, U_stride, meta, M, d, s);
+    case 4: return probe_impl<T, 4, D, 4>(uops, U_stride, meta, M, d, s);
+    case 8: return probe_impl<T, 4, D, 8>(uops, U_stride, meta, M, d, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_probe(bool fp64, int K, int D, const uint2* uops, int U_stride, ProgMeta* meta,
                         int M, const DataArgs& d, hipStream_t s) {
   (void)K;
-  if (fp64) return probe_impl<double, 4, 8>(uops, U_stride, meta, M, d, s);
-  if (D <= 4) return probe_impl<float, 4, 4>(uops, U_stride, meta, M, d, s);
-  return probe_impl<float, 4, 8>(uops, U_stride, meta, M, d, s);
+  const int NP = uop_pairs(U_stride - 2);  // U_stride = L_max + 2; at most L_max + 1 uops
+  if (fp64) return probe_np<double, 8>(NP, uops, U_stride, meta, M, d, s);
+  if (D <= 4 && NP == 1) return probe_impl<float, 4, 4, 1>(uops, U_stride, meta, M, d, s);
+  return probe_np<float, 8>(NP, uops, U_stride, meta, M, d, s);
 }
 
 int lds_limit_bytes() {
