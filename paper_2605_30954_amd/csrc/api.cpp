@@ -282,7 +282,10 @@ AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
   TileCfg& b = a.reg_b;
   b = r;
   b.K = 2;
-  b.G = std::max(1, std::min(4, s.M));
+  // with a path tier, tier B holds only the path tier's few fallen-back
+  // programs: one per group, so that their flagged spans run in parallel
+  // blocks rather than one after another in one block
+  b.G = path ? 1 : std::max(1, std::min(4, s.M));
   while (b.G > 1 && adjoint_reg_lds_bytes(s.F, b.R, b.G, Cm, b.W, a.lane_consts, b.W) > size_t(cap)) --b.G;
   b.n_groups = std::min((s.M + b.G - 1) / b.G, 32);
   a.need_wide = (beyond_path &&
