@@ -196,3 +196,30 @@ def test_clamped_exp_chain_gradient():
     assert np.all(st == 0), st
     assert np.all(np.isfinite(fit)), fit
     assert np.array_equal(grad, np.zeros_like(grad)), grad
+
+
+def test_gradient_graph_replays_match_eager():
+    """A captured gradient call replayed several times, with eager calls, other
+    work on the stream and synchronisations in between: every replay equals
+    the eager result bitwise (the path tier's fallback appends to the tape
+    tiers' lists with atomics; the partials must not depend on that order)."""
+    import torch
+    cfg = get_config(2)
+    d = make_inputs(cfg, 256, 30011, salt=5)
+    ops, cs, X, y = to_device(d)
+    log("[case] grad graph replays cfg2 M=256 N=30011")
+    s = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(s):
+        eager = gg.grad_consts(ops, cs, X, y, graph=False, return_status=True)
+        for k in range(4):
+            outs.append(gg.grad_consts(ops, cs, X, y, return_status=True))  # capture, then replays
+            junk = torch.randn(1 << 20, device="cuda:0") * float(k + 1)      # other work on the stream
+            outs.append(gg.grad_consts(ops, cs, X, y, graph=False, return_status=True))
+            s.synchronize()
+            del junk
+    s.synchronize()
+    ref = [t.cpu().numpy() for t in eager]
+    for o in outs:
+        for a, b in zip(ref, [t.cpu().numpy() for t in o]):
+            assert np.array_equal(a, b, equal_nan=True)
