@@ -512,6 +512,11 @@ int run_call(const Call& c) {
   }
   if (c.with_grad && !adjoint_plan_fits(c.s, ac))
     return fail(GPGOMEA_E_UNSUPPORTED, "no adjoint block fits LDS for L_max=%d, F=%d", c.s.L_max, c.s.F);
+  // the forward kernel's per-group metadata table and the path kernel's
+  // lane-held group list have 64 entries
+  if (fc.G > 64 || (c.with_grad && ac.nc_p > 0 && ac.path.G > 64))
+    return fail(GPGOMEA_E_UNSUPPORTED, "group of more than 64 programs (forward %d, path %d)", fc.G,
+                ac.path.G);
   const bool graph =
       !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr && !g_prof;
   if (!graph) return enqueue_fused(c, fc, ac);
