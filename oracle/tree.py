@@ -56,6 +56,12 @@ def active_constants(genes_row, height: int):
     return out
 
 
+def _chain(f, t):
+    """Chain-rule product f * t with 0 * anything = 0 (see Evaluator)."""
+    with np.errstate(all="ignore"):
+        return np.where((f == 0) | (t == 0), 0.0, f * t)
+
+
 class Evaluator:
     """Float64 tree walk over all rows of X (float64 [F, N]).
 
@@ -67,7 +73,12 @@ class Evaluator:
     record    a list; every decision input (guard / clamp / overflow) is
               appended as (array, threshold)
     duals     if True also return d value / d constant for every active
-              constant, shape [C, N], constants in post-order
+              constant, shape [C, N], constants in post-order.  The chain
+              rule's products absorb zeros: a local partial of exactly 0 (a
+              guarded branch, a saturated clamp) times anything is 0, and so is
+              anything times a tangent of exactly 0, even where the other
+              factor is infinite (a node value that overflowed and is absorbed
+              above it); elsewhere the product is the plain one
     """
 
     def __init__(self, X, rng="f32", perturb=None, record=None, duals=False):
@@ -114,9 +125,9 @@ class Evaluator:
             pa, pb = O.partials(g, a, b, v)
             with np.errstate(all="ignore"):
                 if da is not None:
-                    d = pa[None, :] * da
+                    d = _chain(pa[None, :], da)
                 if db is not None:
-                    d = pb[None, :] * db if d is None else d + pb[None, :] * db
+                    d = _chain(pb[None, :], db) if d is None else d + _chain(pb[None, :], db)
         if self.perturb is not None:
             r, eps = self.perturb
             f = 1.0 + eps * r.uniform(-1.0, 1.0, self.N)

@@ -106,3 +106,26 @@ def test_forward_mode_matches_central_fd_on_population():
         assert np.max(np.abs(gr - f1)) <= tol, m
         checked += 1
     assert checked >= 20
+
+
+def test_zero_partial_absorbs_an_overflowed_factor():
+    """q = x2 / (exp(c x0) * (x1 * x1)) with x1 * x1 beyond the binary32
+    range: the denominator is infinite in the range emulation and q = 0 on
+    every row, whatever c is.  Along the way, the partial of the product
+    with respect to exp(c x0) is x1 * x1 = inf while exp's tangent is exactly
+    0 (c x0 is beyond the clamp).  The derivative is 0 (central differences
+    of the constant q = 0), not the NaN of a plain inf * 0."""
+    N = 64
+    X = np.stack([np.full(N, 100.0), np.full(N, 1e20), np.ones(N)])
+    y = np.random.default_rng(3).standard_normal(N)
+    toks = [V2, C, V0, O.MUL, O.EXP, V1, V1, O.MUL, O.MUL, O.DIV]
+    g, gc = genotype(toks, [1.0])
+    s, gr = GR.gradient(g, gc, 5, X, y, linear_scaling=False, rng="f32")
+    p = TR.evaluate(g, gc, 5, X, rng="f32")
+    assert np.all(p == 0.0) and s["status"] == 0
+    fd = GR.fd_gradient(g, gc, 5, X, y, h=1e-4, linear_scaling=False, rng="f32")
+    assert np.array_equal(fd, [0.0])
+    assert np.array_equal(gr, [0.0]), gr
+    # and the product rule itself: 0 * inf and inf * 0 give 0, finite factors multiply
+    assert np.array_equal(TR._chain(np.array([0.0, np.inf, 2.0]), np.array([np.inf, 0.0, 3.0])),
+                          [0.0, 0.0, 6.0])
