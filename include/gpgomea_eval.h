@@ -11,8 +11,8 @@
  *   or the MSE after the least-squares affine fit y ~ a + b*p (linear scaling;
  *   App. A.2 notes the paper's GPU path lacks it), with NMSE = fitness/Var(y)
  *   (Eq. 2, population variance).  gpgomea_grad_consts adds the gradient of
- *   that fitness with respect to every constant of every individual
- *   (reverse mode; not in the paper).  The batch is the set of changed
+ *   that fitness with respect to every constant of every individual (path
+ *   forward mode over the tree's root-to-constant paths; not in the paper).  The batch is the set of changed
  *   offspring that Alg. 1 collects before its single Evaluate call.
  *
  * Conventions common to all entry points
@@ -107,15 +107,19 @@ int gpgomea_eval_batch(const int8_t* ops, int32_t M, int32_t L_max, const float*
 /* Fitness and its gradient with respect to every constant.
  *   Same inputs and outputs as gpgomea_eval_batch, plus
  *   grad     device double [M][C_max] out: d fitness / d consts[i][j]; zero for
- *            unused constants and for individuals with status != 0.
+ *            unused constants and for individuals with status != 0.  May be
+ *            NULL when C_max = 0 (there is nothing to differentiate).
  * With linear scaling the gradient is (2b/N) sum_r (a + b p_r - y_r) dp_r/dc_j
  * (the optimal a, b have zero partials); without it (2/N) sum_r (p_r - y_r)
  * dp_r/dc_j.  A protected operator's guarded branch and a clamp outside its
- * range have derivative 0; sqrt|a| has derivative 0 at a = 0.  Per-row
- * partials are carried in binary32 and summed in binary64: where a per-row
- * partial exceeds the binary32 range the entry is +-inf or NaN while the
- * fitness stays valid (status 0).  FP64_NODES is not supported here
- * (E_UNSUPPORTED). */
+ * range have derivative 0 (a zero partial ends every derivative path through
+ * it); sqrt|a| has derivative 0 at a = 0.  Node values are the binary32 ones
+ * of the fitness; the chain-rule products dp_r/dc_j are formed in binary32 and
+ * the terms summed in binary64.  Where a row span's binary32 sums are not
+ * finite (a product formed from the leaves up left the binary32 range) that
+ * span is recomputed with binary64 chain-rule products; an entry stays +-inf
+ * or NaN only where the binary64 products overflow too.  FP64_NODES is not
+ * supported here (E_UNSUPPORTED). */
 int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
                         int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
                         const float* y, uint32_t flags, double* fitness, double* aux,
@@ -156,8 +160,11 @@ int gpgomea_validate(const int8_t* ops, int32_t M, int32_t L_max, int32_t C_max,
 
 /* ---- tuning -----------------------------------------------------------------
  * gpgomea_autotune: time the fused kernels over their launch parameters
- * (rows per lane, waves per block, rows per LDS tile, individuals per group)
- * on the given device inputs, keep the fastest choice for this problem class
+ * (forward: rows per lane, rows per LDS tile, individuals per group; adjoint:
+ * rows per LDS tile, entries per group, rows per lane of each constant class)
+ * on a prefix of at most 2^20 rows of the given device inputs, keep the
+ * fastest choice for this problem class (precision, log2 L_max, F, log2 N,
+ * log2 M, gradient or not)
  * in the process-wide table and, if cache_path is not NULL, merge it into that
  * JSON file.  Synchronises `stream`.  `trials` = timed repetitions per
  * candidate (>= 1).  Writes a one-line description of the choice to
@@ -172,8 +179,17 @@ int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, const float* c
  * table (E_ARG if unreadable). */
 int gpgomea_load_tuning(const char* cache_path);
 
-/* Drop every cached hipGraph (they are keyed by shapes, pointers and flags). */
+/* Graph cache.  A call on a non-default stream (without NO_GRAPH) runs as one
+ * hipGraph launch.  Executable graphs are cached per (stream, shapes other
+ * than M, flags, launch plan); a call whose pointers or M differ from the
+ * cached graph's captures its launch sequence again and updates the cached
+ * graph in place (after that graph's previous launch has completed), so a
+ * changing batch size or new output buffers reuse it.  At most 16 graphs are
+ * kept; the least recently used is destroyed (after its last launch
+ * completes).  gpgomea_clear_graphs drops them all; gpgomea_graph_count
+ * returns how many are cached. */
 int gpgomea_clear_graphs(void);
+int gpgomea_graph_count(void);
 
 /* ---- measurement -------------------------------------------------------------
  * gpgomea_profile(1): every kernel a later call enqueues is bracketed by a pair

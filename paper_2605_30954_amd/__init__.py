@@ -18,8 +18,8 @@ from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  #
                    MAX_LEN, MAX_CONSTS, MAX_FEATURES, check, last_error, lib)
 
 __all__ = ["eval_batch", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
-           "autotune", "load_tuning", "clear_graphs", "flags_of", "profile", "profile_report", "op_costs",
-           "GPGOMEAFitness", "LibraryError"]
+           "autotune", "load_tuning", "clear_graphs", "graph_count", "flags_of", "profile",
+           "profile_report", "op_costs", "GPGOMEAFitness", "LibraryError"]
 
 
 def _torch():
@@ -50,16 +50,19 @@ def workspace_bytes(M, L_max, C_max, F, N, flags) -> int:
 _WS = {}
 
 
-def _workspace(device, nbytes):
-    """A cached uint8 device buffer per device, grown on demand (256-aligned:
-    the caching allocator hands out 512-byte aligned blocks)."""
+def _workspace(device, stream, nbytes):
+    """A cached uint8 device buffer per (device, stream), grown on demand
+    (256-aligned: the caching allocator hands out 512-byte aligned blocks).
+    It is allocated while ``stream`` is current, so the caching allocator ties
+    it to that stream: when it is replaced by a larger one, its memory is
+    reused only by work ordered after the calls that used it.  One workspace
+    serves one stream; calls on one stream never overlap."""
     torch = _torch()
-    key = str(device)
+    key = (str(device), int(stream.cuda_stream))
     buf = _WS.get(key)
     if buf is None or buf.numel() < nbytes:
-        if buf is not None:
-            clear_graphs()  # graphs captured against the old buffer
-        buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
+        with torch.cuda.stream(stream):
+            buf = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=device)
         _WS[key] = buf
     return buf
 
@@ -95,9 +98,8 @@ def _prep(ops, consts, X, y):
     return ops, consts, X, y, dev, int(M), int(L), int(consts.shape[1]), int(F), int(N)
 
 
-def _stream_ptr(dev):
-    torch = _torch()
-    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+def _stream(dev):
+    return _torch().cuda.current_stream(dev)
 
 
 def eval_batch(ops, consts, X, y, linear_scaling=True, fp64_nodes=False, plain=False,
@@ -112,12 +114,12 @@ def eval_batch(ops, consts, X, y, linear_scaling=True, fp64_nodes=False, plain=F
     fit = torch.empty(M, dtype=torch.float64, device=dev)
     aux = torch.empty((M, 4), dtype=torch.float64, device=dev) if return_aux else None
     st = torch.empty(M, dtype=torch.int8, device=dev)
-    nb = workspace_bytes(M, L, C, F, N, flags)
-    ws = _workspace(dev, nb)
+    s = _stream(dev)
+    ws = _workspace(dev, s, workspace_bytes(M, L, C, F, N, flags))
     check(lib.gpgomea_eval_batch(
         ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
         y.data_ptr(), flags, fit.data_ptr(), aux.data_ptr() if aux is not None else None,
-        st.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev)))
+        st.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.c_void_p(s.cuda_stream)))
     out = [fit]
     if return_aux:
         out.append(aux)
@@ -137,12 +139,13 @@ def grad_consts(ops, consts, X, y, linear_scaling=True, plain=False, graph=True,
     grad = torch.empty((M, C), dtype=torch.float64, device=dev)
     aux = torch.empty((M, 4), dtype=torch.float64, device=dev) if return_aux else None
     st = torch.empty(M, dtype=torch.int8, device=dev)
-    nb = workspace_bytes(M, L, C, F, N, flags)
-    ws = _workspace(dev, nb)
+    s = _stream(dev)
+    ws = _workspace(dev, s, workspace_bytes(M, L, C, F, N, flags))
     check(lib.gpgomea_grad_consts(
         ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
         y.data_ptr(), flags, fit.data_ptr(), aux.data_ptr() if aux is not None else None,
-        grad.data_ptr(), st.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev)))
+        grad.data_ptr() if C else None, st.data_ptr(), ws.data_ptr(), ws.numel(),
+        ctypes.c_void_p(s.cuda_stream)))
     out = [fit, grad]
     if return_aux:
         out.append(aux)
@@ -160,12 +163,14 @@ def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path
     one-line description of the choice."""
     ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
     flags = flags_of(linear_scaling, fp64_nodes)
-    ws = _workspace(dev, workspace_bytes(M, L, C, F, N, flags))
+    s = _stream(dev)
+    ws = _workspace(dev, s, workspace_bytes(M, L, C, F, N, flags))
     desc = ctypes.create_string_buffer(512)
     check(lib.gpgomea_autotune(
         ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
         y.data_ptr(), flags, int(bool(with_grad)), ws.data_ptr(), ws.numel(),
-        cache_path.encode() if cache_path else None, int(trials), desc, 512, _stream_ptr(dev)))
+        cache_path.encode() if cache_path else None, int(trials), desc, 512,
+        ctypes.c_void_p(s.cuda_stream)))
     return desc.value.decode()
 
 
@@ -179,6 +184,11 @@ def load_tuning(cache_path):
 
 def clear_graphs():
     check(lib.gpgomea_clear_graphs())
+
+
+def graph_count() -> int:
+    """Number of executable graphs the library holds (at most 16)."""
+    return int(lib.gpgomea_graph_count())
 
 
 def profile(enable: bool):
@@ -204,7 +214,8 @@ def op_costs(iters=2048, device="cuda:0"):
     torch = _torch()
     scratch = torch.empty(2048, dtype=torch.float32, device=device)
     out = (ctypes.c_double * 17)()
-    check(lib.gpgomea_op_costs(out, 17, int(iters), scratch.data_ptr(), _stream_ptr(scratch.device)))
+    check(lib.gpgomea_op_costs(out, 17, int(iters), scratch.data_ptr(),
+                               ctypes.c_void_p(_stream(scratch.device).cuda_stream)))
     names = {1: "add", 2: "sub", 3: "rsub", 4: "mul", 5: "div", 6: "rdiv", 7: "pow", 8: "rpow",
              9: "sin", 10: "cos", 11: "sq", 12: "sqrt", 13: "exp", 14: "log", 16: "moments"}
     return {v: out[k] for k, v in names.items()}

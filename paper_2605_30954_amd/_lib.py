@@ -34,6 +34,7 @@ SIGNATURES = {
                                     _i32, _p, _sz, _c.c_char_p, _i32, _c.c_char_p, _i32, _p]),
     "gpgomea_load_tuning": (_c.c_int, [_c.c_char_p]),
     "gpgomea_clear_graphs": (_c.c_int, []),
+    "gpgomea_graph_count": (_c.c_int, []),
     "gpgomea_profile": (_c.c_int, [_i32]),
     "gpgomea_profile_report": (_c.c_int, [_c.c_char_p, _i32]),
     "gpgomea_op_costs": (_c.c_int, [_p, _i32, _i32, _p, _p]),

@@ -23,9 +23,10 @@ namespace gg {
 namespace {
 
 constexpr int kMaxSpans = 256;    // forward partial sums per individual (upper bound)
-constexpr int kMaxAdjSpans = 256;  // gradient partials per individual (upper bound)
-constexpr int64_t kAdjPartEntries = int64_t(1) << 24;  // cap on M x spans x C_max (128 MB)
+constexpr int kMaxAdjSpans = 256;  // gradient partials per (individual, constant) (upper bound)
+constexpr int64_t kAdjPartEntries = int64_t(1) << 26;  // cap on M x C_max x spans (512 MB)
 constexpr int kPlainMaxBlocks = 1024;
+constexpr int kPlainAdjSpans = 1024;  // spans (blocks) of one plain-form adjoint launch
 constexpr uint32_t kKnownFlags =
     GPGOMEA_LINEAR_SCALING | GPGOMEA_FP64_NODES | GPGOMEA_PLAIN | GPGOMEA_NO_GRAPH;
 
@@ -48,65 +49,69 @@ int check_shape(const Shape& s) {
     return fail(GPGOMEA_E_SHAPE, "F=%d outside [1, %d]", s.F, GPGOMEA_MAX_FEATURES);
   if (s.N < 1 || s.N > (int64_t(1) << 40)) return fail(GPGOMEA_E_SHAPE, "N=%lld out of range", (long long)s.N);
   if (s.ldx < s.N) return fail(GPGOMEA_E_SHAPE, "ldx=%lld < N=%lld", (long long)s.ldx, (long long)s.N);
-  if (int64_t(s.M) * (kMaxSpans + 1) > (int64_t(1) << 31))
+  if (int64_t(s.M) * (kMaxSpans + 1) > (int64_t(1) << 31) || int64_t(s.M) * kAdjChunks * 8 > (int64_t(1) << 31))
     return fail(GPGOMEA_E_SHAPE, "M=%d too large", s.M);
   return GPGOMEA_OK;
 }
 
 // stack slots needed by the deepest program that fits in L_max tokens:
-// floor(log2((L_max + 1) / 2)) binary levels
+// floor(log2((L_max + 1) / 2)) binary levels (an upper bound)
 int slots_for(int L_max) {
   int leaves = (L_max + 1) / 2, d = 0;
   while ((1 << (d + 1)) <= leaves) ++d;
   return std::max(d, 1);
 }
 
-// Gradient partials per individual: at most kMaxAdjSpans, and few enough that
-// the partial buffer stays within kAdjPartEntries doubles.
+// Gradient spans: at most kMaxAdjSpans, and few enough that the partial
+// buffer [M][C_max][spans] stays within kAdjPartEntries doubles.
 int adj_span_cap(const Shape& s) {
   const int64_t per = int64_t(s.M) * std::max(s.C_max, 1);
   return int(std::max<int64_t>(1, std::min<int64_t>(kMaxAdjSpans, kAdjPartEntries / per)));
 }
+int plain_adj_spans(int64_t N, int R) {
+  return int(std::max<int64_t>(1, std::min<int64_t>(kPlainAdjSpans, (N + R - 1) / R)));
+}
 
 struct Layout {
-  size_t stats, yscr, meta, uops, merges, ab, part, plain_part, ticket, gpart, adjl, redo_span, tune,
-      total;
-  int U_stride;
-  int MT;  // merge descriptors per program
+  size_t stats, yscr, meta, uops, events, ab, part, plain_part, ticket, gpart, lists, counts, redo,
+      redo_span, plist, pcount, pfb, pfbc, pgpart, pspan, tune, total;
+  int U_stride, ET, lstride, adj_spans;
 };
 
 Layout layout_of(const Shape& s) {
   Layout l{};
   l.U_stride = s.L_max + 2;
+  l.ET = std::max(1, s.L_max);  // flush events per program: at most L_max - 1
+  l.lstride = s.M * kAdjChunks;
+  l.adj_spans = adj_span_cap(s);
+  const size_t M = size_t(s.M), Cm = size_t(std::max(s.C_max, 1));
   size_t o = 0;
-  l.stats = o;
-  o = align256(o + ST_COUNT * sizeof(double));
-  l.yscr = o;
-  o = align256(o + 3 * kStatBlocks * sizeof(double));
-  l.meta = o;
-  o = align256(o + size_t(s.M) * sizeof(ProgMeta));
-  l.uops = o;
-  o = align256(o + size_t(s.M) * l.U_stride * sizeof(uint2));
-  l.MT = std::max(1, s.C_max);
-  l.merges = o;
-  o = align256(o + size_t(s.M) * l.MT * sizeof(uint32_t));
-  l.ab = o;
-  o = align256(o + size_t(s.M) * 2 * sizeof(double));
-  l.part = o;
-  o = align256(o + size_t(s.M) * kMaxSpans * 4 * sizeof(double));
-  l.plain_part = o;
-  o = align256(o + size_t(kPlainMaxBlocks) * 4 * sizeof(double));
-  l.ticket = o;
-  o = align256(o + 64);
-  l.gpart = o;
-  o = align256(o + size_t(s.M) * adj_span_cap(s) * std::max(s.C_max, 1) * sizeof(double));
-  l.adjl = o;  // adjoint tier lists [4][M], counts [4], then the path redo flags [M], or
-               // per-individual counts [M][4] + a list
-  o = align256(o + size_t(s.M) * 8 * sizeof(int32_t) + 64);
-  l.redo_span = o;  // path tier fallback: [M][n_spans] bytes
-  o = align256(o + size_t(s.M) * kMaxAdjSpans);
-  l.tune = o;  // outputs of the autotuner's trial calls: fitness, grad, status
-  o = align256(o + size_t(s.M) * (std::max(s.C_max, 1) + 2) * sizeof(double));
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  l.stats = take(ST_COUNT * sizeof(double));
+  l.yscr = take(3 * kStatBlocks * sizeof(double));
+  l.meta = take(M * sizeof(ProgMeta));
+  l.uops = take(M * l.U_stride * sizeof(uint2));
+  l.events = take(M * l.ET * sizeof(uint2));
+  l.ab = take(M * AB_WORDS * sizeof(double));
+  l.part = take(M * kMaxSpans * 4 * sizeof(double));
+  l.plain_part = take(size_t(kPlainMaxBlocks) * 4 * sizeof(double));
+  l.ticket = take(64);
+  l.gpart = take(M * Cm * l.adj_spans * sizeof(double));
+  l.lists = take(size_t(kAdjClasses + 2) * l.lstride * sizeof(int32_t));  // classes, then 2 fallback
+  l.counts = take(16 * sizeof(int32_t));
+  l.redo = take(M * kAdjChunks * sizeof(int32_t));
+  l.redo_span = take(M * kAdjChunks * l.adj_spans);
+  l.plist = take(M * kAdjChunks * sizeof(int32_t));  // plain form: per-individual entries
+  l.pcount = take(M * sizeof(int32_t));
+  l.pfb = take(M * 2 * kAdjChunks * sizeof(int32_t));
+  l.pfbc = take(M * 2 * sizeof(int32_t));
+  l.pgpart = take(Cm * kPlainAdjSpans * sizeof(double));  // one individual's partials
+  l.pspan = take(size_t(kAdjChunks) * kPlainAdjSpans);
+  l.tune = take(M * (Cm + 2) * sizeof(double));  // outputs of the autotuner's trial calls
   l.total = o;
   return l;
 }
@@ -127,10 +132,11 @@ TuneKey tune_key(const Shape& s, bool grad) {
   return {int((s.flags & GPGOMEA_FP64_NODES) != 0), log2cls(s.L_max + 1), s.F, log2cls(s.N),
           log2cls(s.M), int(grad)};
 }
+// Forward: K rows per lane, R rows per tile, G individuals per group.
+// Adjoint: R, G common to the path classes; K = bit mask of the classes 0-2
+// that run 2 rows per lane instead of 4 (classes 3 and 4 always run 2).
 struct Tuned {
   int K, R, G;
-  int TC;  // adjoint: tier A tape entries when F = 0 (0 for the forward)
-  int F;   // adjoint: path tier constants NC (K, R, G are then the path tier's); 0 = no path tier
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuned> g_tuned;  // forward choices
@@ -150,8 +156,7 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   TileCfg c;
   const bool fp64 = (s.flags & GPGOMEA_FP64_NODES) != 0;
   c.K = fp64 ? 4 : 8;
-  c.D = fp64 ? 8 : (slots_for(s.L_max) <= 4 ? 4 : 8);
-  c.NP = uop_pairs(s.L_max);
+  c.D = slots_for(s.L_max) <= 4 ? 4 : 8;  // plain form's stack slots
   c.W = 4;
   const int BR = 64 * c.K;
   const int64_t Nr = (s.N + BR - 1) / BR * BR;
@@ -180,186 +185,106 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   return c;
 }
 
-// Adjoint plan.  Path tier: programs with at most NC constants in path
-// forward mode, (K, NC) = (4, 12) unless tuned to (4, 16), (4, 8), (8, 8),
-// (2, 16) or (2, 32).
-// Tier A: K rows per lane with a TC-entry register tape, (K, TC) = (4, 16)
-// unless tuned (without a path tier) to (2, 16) or (2, 32).  W = 4 waves; a
-// row tile of at most 32 KB untuned, so that several blocks share a CU.
-// Tier B: (2, 32) for the tapes between tier A's and 32 entries.  Tier C: the
-// largest LDS-tape block that fits the worst-case tape (L_max - 1 entries per
-// wave).  All tiers use the same spans, set by the path tier (tier A without
-// one); the other tiers' tiles divide the span.
-bool reg_variant(int K, int TC) { return (K == 4 && TC == 16) || (K == 2 && (TC == 16 || TC == 32)); }
-bool path_variant(int K, int NC) {
-  return (K == 4 && (NC == 16 || NC == 12 || NC == 8)) || (K == 8 && NC == 8) ||
-         (K == 2 && (NC == 32 || NC == 16));
-}
+// Adjoint plan: the path classes share the row tile R (a multiple of 256,
+// every class's batch), the group size G and the spans; class c's grid holds
+// n_groups[c] group slots per span (blocks loop over the groups of their
+// slot).  The fallback pass uses small groups, so that the flagged spans of
+// different entries run in parallel blocks.
+struct AdjPlan {
+  int R = 512, G = 32;
+  int Kmask = 0;  // classes 0-2 with bit c set run 2 rows per lane, else 4
+  int n_spans = 1, tiles_per_span = 1;
+  int64_t span_rows = 0;
+  bool on[kAdjClasses] = {false, false, false, false, false};
+  int n_groups[kAdjClasses] = {1, 1, 1, 1, 1};
+  int fb_G = 4, fb_groups = 1;
+  int plain_spans = 1;
+  int64_t plain_span_rows = 0;
+};
 
-AdjPlan plan_adjoint(const Shape& s, int D, const Tuned* t, int span_cap) {
+AdjPlan plan_adjoint(const Shape& s, const Tuned* t, int span_cap) {
   AdjPlan a;
-  const int Cm = std::max(1, s.C_max);
-  const int cap = lds_limit_bytes() - 64;  // static LDS of the kernels
-  TileCfg& pt = a.path;
-  TileCfg& r = a.reg;
-  pt.D = r.D = D;
-  pt.NP = r.NP = uop_pairs(s.L_max);
-  pt.W = r.W = 4;
-  pt.K = 4;
-  a.nc_p = 12;  // (4, 12) is the largest variant that keeps three waves per SIMD
-  pt.G = 16;
-  pt.R = 1024;
-  r.K = 4;
-  a.tc_a = 16;
-  a.tc_b = 32;
-  a.lane_consts = std::min(Cm, 32);
-  r.G = 16;
-  r.R = 1024;
   if (t) {
-    if (t->F > 0 && path_variant(t->K, t->F)) {
-      pt.K = t->K;
-      a.nc_p = t->F;
-      pt.R = t->R;
-      pt.G = t->G;
-    } else if (t->F == 0) {
-      a.nc_p = 0;
-      if (reg_variant(t->K, t->TC)) {
-        r.K = t->K;
-        a.tc_a = t->TC;
-      }
-      r.R = t->R;
-      r.G = t->G;
-    }
+    a.R = t->R;
+    a.G = t->G;
+    a.Kmask = t->K & 7;
   }
-  const bool path = a.nc_p > 0;
-  TileCfg& lead = path ? pt : r;
-  const size_t tile_cap = t ? size_t(cap) : size_t(32 * 1024);
-  auto lead_lds = [&](int R) {
-    return path ? adjoint_path_lds_bytes(s.F, R, lead.G, Cm, lead.W, a.nc_p)
-                : adjoint_reg_lds_bytes(s.F, R, lead.G, Cm, lead.W, a.lane_consts, 1);
-  };
-  while (lead.R > 64 * lead.K &&
-         (size_t(s.F) * lead.R * 4 + size_t(lead.R) * 8 > tile_cap || lead_lds(lead.R) > size_t(cap)))
-    lead.R /= 2;
-  const int64_t Nr = (s.N + 255) / 256 * 256;  // a multiple of every tier's batch
-  if (Nr < lead.R) lead.R = int(Nr);
-  lead.R = std::max(256, lead.R / 256 * 256);
-  // at most 64 programs per group: the path kernel holds a group's list one
-  // entry per lane
-  lead.G = std::max(1, std::min({lead.G, s.M, 64}));
-  lead.n_groups = (s.M + lead.G - 1) / lead.G;
-  // spans: enough blocks to fill the chip many times over (about 16K work
-  // items, down to one row tile each).  The adjoint's cost per (program, tile)
-  // varies with the program, so small items keep the waves of the last rounds
-  // busy; each span costs one partial per (program, constant) in HBM.
-  const int64_t tiles = (s.N + lead.R - 1) / lead.R;
-  int64_t want = (16384 + lead.n_groups - 1) / lead.n_groups;
+  const int cap = lds_limit_bytes() - 64;  // static LDS of the kernels
+  a.R = std::max(256, a.R / 256 * 256);
+  while (a.R > 256 && adjoint_path_lds_bytes(s.F, a.R, 64, kAdjChunkNC, 4, true) > size_t(cap)) a.R /= 2;
+  const int64_t Nr = (s.N + 255) / 256 * 256;
+  if (Nr < a.R) a.R = int(Nr);
+  a.G = std::max(1, std::min({a.G, s.M, 64}));  // the group list is lane-held
+  const int Cm = s.C_max;
+  a.on[0] = Cm >= 1;
+  a.on[1] = Cm > 4;
+  a.on[2] = Cm > 8;
+  a.on[3] = Cm > 16;
+  a.on[4] = Cm >= 1 && s.L_max >= 127;  // five or more stack slots need 64 leaves
+  const int groups = (s.M + a.G - 1) / a.G;
+  for (int c = 0; c < kAdjClasses; ++c) a.n_groups[c] = groups;
+  // spans: enough work items (span, group) to fill the chip many times over
+  // (about 16K); each span costs one partial per (individual, constant)
+  const int64_t tiles = (s.N + a.R - 1) / a.R;
+  int64_t want = (16384 + groups - 1) / groups;
   want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, int64_t(span_cap)}));
-  lead.tiles_per_span = int((tiles + want - 1) / want);
-  a.span_rows = int64_t(lead.tiles_per_span) * lead.R;
+  a.tiles_per_span = int((tiles + want - 1) / want);
+  a.span_rows = int64_t(a.tiles_per_span) * a.R;
   a.n_spans = int((s.N + a.span_rows - 1) / a.span_rows);
-  lead.n_spans = a.n_spans;
-  if (path) {  // tier A: the path tile or a power-of-two fraction of it
-    r.R = pt.R;
-    while (r.R > 64 * r.K && adjoint_reg_lds_bytes(s.F, r.R, r.G, Cm, r.W, a.lane_consts, 1) > size_t(cap))
-      r.R /= 2;
-    r.G = std::max(1, std::min(r.G, s.M));
-    r.n_groups = (s.M + r.G - 1) / r.G;
-    r.n_spans = a.n_spans;
-    r.tiles_per_span = int(a.span_rows / r.R);
-  }
-
-  // A program of L tokens has at most L - 1 tape entries (one per tree edge)
-  // and at most C_max constants, so small shapes never reach tiers A, B or C.
-  a.tape_cap = std::max(1, s.L_max - 1);
-  // with a path tier, individuals whose partials overflow fall back to tier B
-  // (or C for tapes longer than tier B's)
-  const bool beyond_path = !path || Cm > a.nc_p;
-  a.need_a = beyond_path;
-  a.need_b = (beyond_path && a.tape_cap > a.tc_a && a.tc_b > a.tc_a) || path;
-  // tier B: few individuals, each shared by the block's waves; G_b of them
-  // per group, a bounded number of group slots per span (blocks loop)
-  TileCfg& b = a.reg_b;
-  b = r;
-  b.K = 2;
-  // with a path tier, tier B holds only the path tier's few fallen-back
-  // programs: one per group, so that their flagged spans run in parallel
-  // blocks rather than one after another in one block
-  b.G = path ? 1 : std::max(1, std::min(4, s.M));
-  while (b.G > 1 && adjoint_reg_lds_bytes(s.F, b.R, b.G, Cm, b.W, a.lane_consts, b.W) > size_t(cap)) --b.G;
-  b.n_groups = std::min((s.M + b.G - 1) / b.G, 32);
-  a.need_wide = (beyond_path &&
-                 (a.tape_cap > std::max(a.tc_a, a.need_b ? a.tc_b : 0) || Cm > a.lane_consts)) ||
-                (path && a.tape_cap > a.tc_b);
-
-  // tier C: its tile must divide span_rows (powers of two <= r.R)
-  TileCfg& w = a.wide;
-  w.D = 8;
-  bool ok = false;
-  const int Ks[2] = {2, 1};
-  const int Ws[3] = {4, 2, 1};
-  const int Gs[3] = {16, 8, 4};
-  for (int k : Ks) {
-    for (int wv : Ws) {
-      for (int rr = r.R; rr >= 64 * k && !ok; rr /= 2) {
-        if (rr % (64 * k)) continue;
-        for (int g : Gs) {
-          if (adjoint_lds_bytes(s.F, rr, g, Cm, wv, k, a.tape_cap) <= size_t(cap)) {
-            w.K = k;
-            w.W = wv;
-            w.R = rr;
-            w.G = g;
-            ok = true;
-            break;
-          }
-        }
-      }
-      if (ok) break;
-    }
-    if (ok) break;
-  }
-  if (!ok) {  // smallest block; the caller reports the shape as unsupported
-    w.K = 1;
-    w.W = 1;
-    w.R = 64;
-    w.G = 1;
-  }
-  w.G = std::max(1, std::min(w.G, s.M));
-  w.n_groups = std::min((s.M + w.G - 1) / w.G, 16);  // group slots per span; blocks loop
-  w.n_spans = a.n_spans;
-  w.tiles_per_span = int(a.span_rows / w.R);
+  a.fb_G = std::min(4, s.M * kAdjChunks);
+  a.fb_groups = std::min(64, (s.M * kAdjChunks + a.fb_G - 1) / a.fb_G);
+  a.plain_spans = plain_adj_spans(s.N, a.R);
+  const int64_t ptiles = (tiles + a.plain_spans - 1) / a.plain_spans;
+  a.plain_span_rows = ptiles * a.R;
+  a.plain_spans = int((s.N + a.plain_span_rows - 1) / a.plain_span_rows);
   return a;
 }
 
 bool adjoint_plan_fits(const Shape& s, const AdjPlan& a) {
   const int cap = lds_limit_bytes() - 64;
-  const int Cm = std::max(1, s.C_max);
-  if (a.nc_p > 0 && adjoint_path_lds_bytes(s.F, a.path.R, a.path.G, Cm, a.path.W, a.nc_p) > size_t(cap))
-    return false;
-  if (a.need_a && adjoint_reg_lds_bytes(s.F, a.reg.R, a.reg.G, Cm, a.reg.W, a.lane_consts, 1) > size_t(cap))
-    return false;
-  if (a.need_b &&
-      adjoint_reg_lds_bytes(s.F, a.reg_b.R, a.reg_b.G, Cm, a.reg_b.W, a.lane_consts, a.reg_b.W) > size_t(cap))
-    return false;
-  if (!a.need_wide) return true;
-  return adjoint_lds_bytes(s.F, a.wide.R, a.wide.G, std::max(1, s.C_max), a.wide.W, a.wide.K,
-                           a.tape_cap) <= size_t(cap) &&
-         a.span_rows % a.wide.R == 0;
+  return adjoint_path_lds_bytes(s.F, a.R, a.G, kAdjChunkNC, 4, false) <= size_t(cap) &&
+         adjoint_path_lds_bytes(s.F, a.R, 8, kAdjChunkNC, 4, true) <= size_t(cap);
 }
 
 // ------------------------------------------------------------ graph cache
+// A call on a non-default stream is captured and launched as one hipGraph.
+// The executable graph is cached per (shapes, flags, launch plan), not per
+// pointer or batch size: every call captures its launch sequence again (host
+// work only) and updates the cached executable graph in place
+// (hipGraphExecUpdate: same kernels in the same order, new arguments and grid
+// sizes), so calls with new output buffers or another batch size M reuse it.
+// When the update is refused the graph is instantiated anew.  The cache holds
+// at most kGraphCacheMax executables; the least recently used one is
+// destroyed once its last launch has completed.
+constexpr size_t kGraphCacheMax = 16;
 struct GraphKey {
-  std::vector<uintptr_t> v;
+  std::vector<int64_t> v;
   bool operator<(const GraphKey& o) const { return v < o.v; }
 };
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;   // recorded after the last launch
+  uint64_t used = 0;
+  std::vector<uintptr_t> sig;  // pointers and M the executable holds
+};
 std::mutex g_graph_mu;
-std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::map<GraphKey, GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
 
 #define GG_HIP(call)                                                                      \
   do {                                                                                    \
     hipError_t e_ = (call);                                                               \
     if (e_ != hipSuccess) return fail(GPGOMEA_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
+
+void destroy_entry(GraphEntry& e) {
+  if (e.done) {
+    (void)hipEventSynchronize(e.done);
+    (void)hipEventDestroy(e.done);
+  }
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  e = GraphEntry{};
+}
 
 // ------------------------------------------------------- kernel timing hook
 // With profiling on, every launch of a call is bracketed by hipEvents on the
@@ -410,149 +335,184 @@ struct Call {
   bool with_grad;
 };
 
-// Enqueue the whole fused pipeline on c.stream.
+const char* const kClassName[kAdjClasses] = {"adjoint_c4", "adjoint_c8", "adjoint_c16", "adjoint_c32",
+                                             "adjoint_deep"};
+
+// Enqueue the whole pipeline on c.stream.
 int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   const Layout l = layout_of(c.s);
   const bool fp64 = (c.s.flags & GPGOMEA_FP64_NODES) != 0;
-  double* stats = reinterpret_cast<double*>(c.ws + l.stats);
-  double* yscr = reinterpret_cast<double*>(c.ws + l.yscr);
-  ProgMeta* meta = reinterpret_cast<ProgMeta*>(c.ws + l.meta);
-  uint2* uops = reinterpret_cast<uint2*>(c.ws + l.uops);
-  uint32_t* merges = reinterpret_cast<uint32_t*>(c.ws + l.merges);
-  double* ab = reinterpret_cast<double*>(c.ws + l.ab);
-  double* part = reinterpret_cast<double*>(c.ws + l.part);
-  double* gpart = reinterpret_cast<double*>(c.ws + l.gpart);
+  char* ws = c.ws;
+  double* stats = reinterpret_cast<double*>(ws + l.stats);
+  double* yscr = reinterpret_cast<double*>(ws + l.yscr);
+  ProgMeta* meta = reinterpret_cast<ProgMeta*>(ws + l.meta);
+  uint2* uops = reinterpret_cast<uint2*>(ws + l.uops);
+  uint2* events = reinterpret_cast<uint2*>(ws + l.events);
+  double* ab = reinterpret_cast<double*>(ws + l.ab);
+  double* part = reinterpret_cast<double*>(ws + l.part);
+  double* gpart = reinterpret_cast<double*>(ws + l.gpart);
+  int* lists = reinterpret_cast<int*>(ws + l.lists);
+  int* counts = reinterpret_cast<int*>(ws + l.counts);
+  int* redo = reinterpret_cast<int*>(ws + l.redo);
+  uint8_t* redo_span = reinterpret_cast<uint8_t*>(ws + l.redo_span);
   const DataArgs d{c.X, c.s.ldx, c.s.F, c.s.N, c.y};
-  const int D = fp64 ? 8 : fc.D;
+  const int M = c.s.M;
+  const bool grad_work = c.with_grad && c.s.C_max > 0;
   GG_TIMED("ystats", launch_ystats(c.y, c.s.N, stats, yscr, c.stream));
-  GG_TIMED("compile", launch_compile(c.ops, c.s.M, c.s.L_max, c.consts, c.s.C_max, c.s.F, D, l.U_stride,
-                                     uops, meta, merges, l.MT, c.stream));
-  GG_TIMED("probe", launch_probe(fp64, fc.K, D, uops, l.U_stride, meta, c.s.M, d, c.stream));
+  GG_TIMED("compile", launch_compile(c.ops, M, c.s.L_max, c.consts, c.s.C_max, c.s.F, 8, l.U_stride,
+                                     uops, meta, events, l.ET, c.stream));
+  GG_TIMED("probe", launch_probe(fp64, uops, l.U_stride, meta, M, d, c.stream));
   const bool sse = c.aux != nullptr || !(c.s.flags & GPGOMEA_LINEAR_SCALING);
+
+  // one launch of an adjoint class over `list`
+  auto adj = [&](int cls, int K, const int* list, const int* count, int G, int n_groups, int n_spans,
+                 int64_t span_rows, double* gp, int gstride, int gi0, uint8_t* rspan, int rstride, int ebase,
+                 int* fbl, int* fbc, int fbs, bool split) {
+    AdjLaunch L{cls, K, uops, l.U_stride, meta, d, stats, ab, gp, c.s.C_max, gstride, gi0, list, count,
+                ac.R, G, n_groups, n_spans, span_rows, events, l.ET, redo, rspan, rstride, ebase, fbl, fbc,
+                fbs, split};
+    return launch_adjoint_class(L, c.stream);
+  };
+
   if (c.s.flags & GPGOMEA_PLAIN) {
-    unsigned* ticket = reinterpret_cast<unsigned*>(c.ws + l.ticket);
-    double* pp = reinterpret_cast<double*>(c.ws + l.plain_part);
+    // one launch per individual: forward (last block finalizes), then its
+    // gradient: the path kernel with the block's waves sharing the
+    // individual, its binary64 fallback, and its gradient finalize
+    unsigned* ticket = reinterpret_cast<unsigned*>(ws + l.ticket);
+    double* pp = reinterpret_cast<double*>(ws + l.plain_part);
     GG_HIP(launch_fill_u32(ticket, 1, 0u, c.stream));
-    for (int i = 0; i < c.s.M; ++i)
+    for (int i = 0; i < M; ++i)
       GG_TIMED("plain_forward", launch_plain_forward(fp64, fc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
                                                      c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
-    if (c.with_grad) {
-      // the plain form differentiates with the tape tiers only
-      const Tuned tape_only{4, 1024, 16, 16, 0};
-      const AdjPlan one = plan_adjoint(Shape{1, c.s.L_max, c.s.C_max, c.s.F, c.s.N, c.s.ldx, c.s.flags}, D,
-                                       &tape_only, adj_span_cap(c.s));
-      int* pcounts = reinterpret_cast<int*>(c.ws + l.adjl);
-      int* list0 = pcounts + 4 * size_t(c.s.M);
-      GG_TIMED("plain_tiers", launch_adjoint_tier_flags(one, meta, ab, c.s.M, pcounts, list0, c.stream));
-      for (int i = 0; i < c.s.M; ++i) {
-        const uint2* ui = uops + size_t(i) * l.U_stride;
-        double* gi = gpart + size_t(i) * one.n_spans * c.s.C_max;
-        const double* abi = ab + 2 * size_t(i);
-        const int* ci = pcounts + 4 * size_t(i);
-        if (one.need_a)
-          GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 0, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
-                                                       stats, abi, gi, list0, ci + 0, nullptr, nullptr,
-                                                       c.stream));
-        if (one.need_b)
-          GG_TIMED("plain_adjoint", launch_adjoint_reg(one, 1, ui, l.U_stride, meta + i, 1, c.s.C_max, d,
-                                                       stats, abi, gi, list0, ci + 1, nullptr, nullptr,
-                                                       c.stream));
-        if (one.need_wide)
-          GG_TIMED("plain_adjoint", launch_adjoint_lds(one, ui, l.U_stride, meta + i, 1, c.s.C_max, d, stats,
-                                                       abi, gi, list0, ci + 2, nullptr, nullptr, c.stream));
+    if (grad_work) {
+      int* plist = reinterpret_cast<int*>(ws + l.plist);
+      int* pcount = reinterpret_cast<int*>(ws + l.pcount);
+      int* pfb = reinterpret_cast<int*>(ws + l.pfb);
+      int* pfbc = reinterpret_cast<int*>(ws + l.pfbc);
+      double* pg = reinterpret_cast<double*>(ws + l.pgpart);
+      uint8_t* pspan = reinterpret_cast<uint8_t*>(ws + l.pspan);
+      GG_TIMED("plain_lists", launch_adjoint_plain_lists(meta, ab, M, plist, pcount, pfbc, redo, c.stream));
+      const int P = ac.plain_spans;
+      for (int i = 0; i < M; ++i) {
+        const int e0 = i * kAdjChunks;
+        int* fb = pfb + 2 * e0;  // this individual's two fallback lists of 8 and their counts
+        int* fbc = pfbc + 2 * i;
+        GG_TIMED("plain_adjoint", adj(kAdjPlain, 2, plist + e0, pcount + i, kAdjChunks, 1, P, ac.plain_span_rows,
+                                      pg, P, i, pspan, P, e0, fb, fbc, kAdjChunks, true));
+        GG_TIMED("plain_fallback", adj(kAdjFallback, 2, fb, fbc, kAdjChunks, 1, P, ac.plain_span_rows, pg, P, i,
+                                       pspan, P, e0, nullptr, nullptr, 0, true));
+        GG_TIMED("plain_fallback", adj(kAdjFallbackWide, 1, fb + kAdjChunks, fbc + 1, kAdjChunks, 1, P,
+                                       ac.plain_span_rows, pg, P, i, pspan, P, e0, nullptr, nullptr, 0, true));
+        GG_TIMED("plain_grad_finalize",
+                 launch_grad_finalize(meta, i, 1, c.s.C_max, pg, P, P, stats, ab, c.grad, c.stream));
       }
-      GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, one.n_spans, stats, ab,
-                                                     c.s.flags, c.status, c.grad, c.stream));
+    } else if (c.with_grad) {  // no constants: nothing to differentiate (grad has no entries)
     }
     return GPGOMEA_OK;
   }
-  GG_TIMED("fused_forward", launch_fused_forward(fp64, fc, uops, l.U_stride, meta, c.s.M, d, stats, part, sse,
+  GG_TIMED("fused_forward", launch_fused_forward(fp64, fc, uops, l.U_stride, meta, M, d, stats, part, sse,
                                                  c.stream));
-  GG_TIMED("finalize", launch_finalize(meta, c.s.M, part, fc.n_spans, stats, c.s.flags, c.fitness, c.aux,
+  GG_TIMED("finalize", launch_finalize(meta, M, part, fc.n_spans, stats, c.s.flags, c.fitness, c.aux,
                                        c.status, ab, c.stream));
-  if (c.with_grad) {
-    int* lists = reinterpret_cast<int*>(c.ws + l.adjl);
-    int* counts = lists + 4 * size_t(c.s.M);
-    const size_t M = size_t(c.s.M);
-    int* redo = counts + 4;  // path fallback flags [M], right after the four counts
-    uint8_t* redo_span = reinterpret_cast<uint8_t*>(c.ws + l.redo_span);
-    int* rd = ac.nc_p > 0 ? redo : nullptr;  // the tape tiers' fallback flags
-    uint8_t* rs = ac.nc_p > 0 ? redo_span : nullptr;
-    GG_TIMED("adjoint_partition", launch_adjoint_partition(ac, meta, ab, c.s.M, lists, counts, rd, c.stream));
-    if (ac.nc_p > 0) {
-      GG_TIMED("adjoint_path", launch_adjoint_path(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                   gpart, merges, l.MT, redo, redo_span, lists, counts,
-                                                   c.stream));
+  if (grad_work) {
+    int* fbl = lists + size_t(kAdjClasses) * l.lstride;  // two fallback lists, lstride apart
+    int* fbc = counts + kAdjClasses;
+    const int S = ac.n_spans, gs = l.adj_spans;
+    GG_TIMED("adjoint_partition",
+             launch_adjoint_partition(meta, ab, M, l.lstride, lists, counts, redo, c.stream));
+    for (int cls = 0; cls < kAdjClasses; ++cls) {
+      if (!ac.on[cls]) continue;
+      const int K = cls >= 3 || ((ac.Kmask >> cls) & 1) ? 2 : 4;
+      GG_TIMED(kClassName[cls], adj(cls, K, lists + size_t(cls) * l.lstride, counts + cls, ac.G, ac.n_groups[cls],
+                                    S, ac.span_rows, gpart, gs, 0, redo_span, gs, 0, fbl, fbc, l.lstride, false));
     }
-    if (ac.need_a)
-      GG_TIMED("adjoint_reg", launch_adjoint_reg(ac, 0, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
-                                                 ab, gpart, lists, counts + 0, nullptr, nullptr, c.stream));
-    if (ac.need_b)
-      GG_TIMED("adjoint_reg_b", launch_adjoint_reg(ac, 1, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats,
-                                                   ab, gpart, lists + M, counts + 1, rd, rs, c.stream));
-    if (ac.need_wide)
-      GG_TIMED("adjoint_lds", launch_adjoint_lds(ac, uops, l.U_stride, meta, c.s.M, c.s.C_max, d, stats, ab,
-                                                 gpart, lists + 2 * M, counts + 2, rd, rs, c.stream));
-    GG_TIMED("grad_finalize", launch_grad_finalize(meta, c.s.M, c.s.C_max, gpart, ac.n_spans, stats, ab,
-                                                   c.s.flags, c.status, c.grad, c.stream));
+    GG_TIMED("adjoint_fallback", adj(kAdjFallback, 2, fbl, fbc, ac.fb_G, ac.fb_groups, S, ac.span_rows, gpart, gs,
+                                     0, redo_span, gs, 0, nullptr, nullptr, 0, false));
+    GG_TIMED("adjoint_fallback", adj(kAdjFallbackWide, 1, fbl + l.lstride, fbc + 1, ac.fb_G, ac.fb_groups, S,
+                                     ac.span_rows, gpart, gs, 0, redo_span, gs, 0, nullptr, nullptr, 0, false));
+    GG_TIMED("grad_finalize",
+             launch_grad_finalize(meta, 0, M, c.s.C_max, gpart, gs, S, stats, ab, c.grad, c.stream));
   }
   return GPGOMEA_OK;
+}
+
+void plans_for(const Shape& s, TileCfg& fc, AdjPlan& ac) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(tune_key(s, false));
+  fc = plan_forward(s, it == g_tuned.end() ? nullptr : &it->second);
+  auto ia = g_tuned_adj.find(tune_key(s, true));
+  ac = plan_adjoint(s, ia == g_tuned_adj.end() ? nullptr : &ia->second, adj_span_cap(s));
 }
 
 int run_call(const Call& c) {
   (void)hipGetLastError();  // launches below report their own errors only
   TileCfg fc;
   AdjPlan ac;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(tune_key(c.s, false));
-    fc = plan_forward(c.s, it == g_tuned.end() ? nullptr : &it->second);
-    auto ia = g_tuned_adj.find(tune_key(c.s, true));
-    ac = plan_adjoint(c.s, fc.D, ia == g_tuned_adj.end() ? nullptr : &ia->second, adj_span_cap(c.s));
-  }
+  plans_for(c.s, fc, ac);
   if (c.with_grad && !adjoint_plan_fits(c.s, ac))
-    return fail(GPGOMEA_E_UNSUPPORTED, "no adjoint block fits LDS for L_max=%d, F=%d", c.s.L_max, c.s.F);
-  // the forward kernel's per-group metadata table and the path kernel's
-  // lane-held group list have 64 entries
-  if (fc.G > 64 || (c.with_grad && ac.nc_p > 0 && ac.path.G > 64))
-    return fail(GPGOMEA_E_UNSUPPORTED, "group of more than 64 programs (forward %d, path %d)", fc.G,
-                ac.path.G);
+    return fail(GPGOMEA_E_UNSUPPORTED, "no adjoint block fits LDS for F=%d", c.s.F);
+  if (fc.G > 64 || ac.G > 64)
+    return fail(GPGOMEA_E_UNSUPPORTED, "group of more than 64 programs (forward %d, adjoint %d)", fc.G, ac.G);
   const bool graph =
       !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr && !g_prof;
   if (!graph) return enqueue_fused(c, fc, ac);
 
+  // the launch sequence depends on these (not on pointers or M)
   GraphKey key;
-  key.v = {uintptr_t(c.with_grad), uintptr_t(c.ops), uintptr_t(c.consts), uintptr_t(c.X),
-           uintptr_t(c.y), uintptr_t(c.fitness), uintptr_t(c.aux), uintptr_t(c.grad),
-           uintptr_t(c.status), uintptr_t(c.ws), uintptr_t(c.s.M), uintptr_t(c.s.L_max),
-           uintptr_t(c.s.C_max), uintptr_t(c.s.F), uintptr_t(c.s.N), uintptr_t(c.s.ldx),
-           uintptr_t(c.s.flags), uintptr_t(fc.K), uintptr_t(fc.R), uintptr_t(fc.G),
-           uintptr_t(ac.reg.R), uintptr_t(ac.reg.G), uintptr_t(ac.reg.K), uintptr_t(ac.tc_a),
-           uintptr_t(ac.n_spans), uintptr_t(ac.nc_p), uintptr_t(ac.path.K), uintptr_t(ac.path.R),
-           uintptr_t(ac.path.G)};
-  hipGraphExec_t exec = nullptr;
-  {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    auto it = g_graphs.find(key);
-    if (it != g_graphs.end()) exec = it->second;
-  }
-  if (!exec) {
+  key.v = {int64_t(c.with_grad), int64_t(c.aux != nullptr), int64_t(c.s.L_max), int64_t(c.s.C_max),
+           int64_t(c.s.F), c.s.N, c.s.ldx, int64_t(c.s.flags), int64_t(fc.K), int64_t(fc.R),
+           int64_t(ac.R), int64_t(ac.Kmask), int64_t(reinterpret_cast<uintptr_t>(c.stream))};
+  const std::vector<uintptr_t> sig = {uintptr_t(c.ops),    uintptr_t(c.consts), uintptr_t(c.X),
+                                      uintptr_t(c.y),      uintptr_t(c.fitness), uintptr_t(c.aux),
+                                      uintptr_t(c.grad),   uintptr_t(c.status), uintptr_t(c.ws),
+                                      uintptr_t(c.s.M)};
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  GraphEntry& e = g_graphs[key];
+  if (!(e.exec && e.sig == sig)) {  // new arguments: capture, then update or instantiate
+    hipGraph_t g = nullptr;
     GG_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
     const int rc = enqueue_fused(c, fc, ac);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(c.stream, &g);
-    if (rc != GPGOMEA_OK) {
+    const hipError_t ec = hipStreamEndCapture(c.stream, &g);
+    if (rc != GPGOMEA_OK || ec != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return rc;
+      if (!e.exec) g_graphs.erase(key);
+      return rc != GPGOMEA_OK ? rc : fail(GPGOMEA_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
     }
-    if (e != hipSuccess) return fail(GPGOMEA_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (e.exec) {
+      // the executable's previous launch must have completed before its
+      // arguments change
+      GG_HIP(hipEventSynchronize(e.done));
+      hipGraphNode_t bad_node = nullptr;
+      hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+      const hipError_t eu = hipGraphExecUpdate(e.exec, g, &bad_node, &res);
+      if (eu != hipSuccess || res != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();
+        destroy_entry(e);
+      }
+    }
+    if (!e.exec) {
+      const hipError_t ei = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        e.exec = nullptr;
+        g_graphs.erase(key);
+        return fail(GPGOMEA_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+      }
+    }
     (void)hipGraphDestroy(g);
-    if (e2 != hipSuccess) return fail(GPGOMEA_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    g_graphs[key] = exec;
+    e.sig = sig;
   }
-  GG_HIP(hipGraphLaunch(exec, c.stream));
+  if (!e.done) GG_HIP(hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
+  GG_HIP(hipGraphLaunch(e.exec, c.stream));
+  GG_HIP(hipEventRecord(e.done, c.stream));
+  e.used = ++g_graph_clock;
+  while (g_graphs.size() > kGraphCacheMax) {  // evict the least recently used
+    auto lru = g_graphs.begin();
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+      if (it->second.used < lru->second.used) lru = it;
+    destroy_entry(lru->second);
+    g_graphs.erase(lru);
+  }
   return GPGOMEA_OK;
 }
 
@@ -606,7 +566,7 @@ extern "C" int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, 
   const Shape s{M, L_max, C_max, F, N, ldx, flags};
   int rc = check_call(s, ops, consts, X, y, fitness, workspace, workspace_bytes);
   if (rc) return rc;
-  if (!grad) return fail(GPGOMEA_E_ARG, "grad is NULL");
+  if (!grad && C_max > 0) return fail(GPGOMEA_E_ARG, "grad is NULL but C_max > 0");
   if (flags & GPGOMEA_FP64_NODES)
     return fail(GPGOMEA_E_UNSUPPORTED, "the adjoint runs in binary32 nodes only");
   Call c{s, ops, consts, X, y, fitness, aux, grad, status, static_cast<char*>(workspace),
@@ -616,9 +576,14 @@ extern "C" int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, 
 
 extern "C" int gpgomea_clear_graphs(void) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : g_graphs) destroy_entry(kv.second);
   g_graphs.clear();
   return GPGOMEA_OK;
+}
+
+extern "C" int gpgomea_graph_count(void) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  return int(g_graphs.size());
 }
 
 // --------------------------------------------------------------- profiling
@@ -714,9 +679,8 @@ std::string tune_line(const char* table, const TuneKey& k, const Tuned& t) {
   char b[256];
   std::snprintf(b, sizeof(b),
                 "  {\"table\": \"%s\", \"fp64\": %d, \"Lcls\": %d, \"F\": %d, \"Ncls\": %d, "
-                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d, \"TC\": %d, "
-                "\"TF\": %d}",
-                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G, t.TC, t.F);
+                "\"Mcls\": %d, \"grad\": %d, \"K\": %d, \"R\": %d, \"G\": %d}",
+                table, k.fp64, k.Lcls, k.F, k.Ncls, k.Mcls, k.grad, t.K, t.R, t.G);
   return b;
 }
 
@@ -748,9 +712,7 @@ bool read_tuning(const char* path, int* n_read) {
           json_int(line, "Mcls", &k.Mcls) && json_int(line, "grad", &k.grad) &&
           json_int(line, "K", &t.K) && json_int(line, "R", &t.R) && json_int(line, "G", &t.G)))
       continue;
-    if (!json_int(line, "TC", &t.TC)) t.TC = 0;
-    if (!json_int(line, "TF", &t.F)) t.F = 0;
-    if (t.K < 1 || t.R < 64 || t.G < 1) continue;
+    if (t.K < 0 || t.R < 64 || t.G < 1 || (fwd && t.K < 1)) continue;
     (fwd ? g_tuned : g_tuned_adj)[k] = t;
     ++n;
   }
@@ -760,7 +722,7 @@ bool read_tuning(const char* path, int* n_read) {
 
 bool write_tuning(const char* path) {
   std::ostringstream o;
-  o << "{\"gpgomea_tuning\": 1, \"entries\": [\n";
+  o << "{\"gpgomea_tuning\": 2, \"entries\": [\n";
   bool first = true;
   for (const auto& e : g_tuned) {
     o << (first ? "" : ",\n") << tune_line("fwd", e.first, e.second);
@@ -806,12 +768,12 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   Call c{st, ops, consts, X, y, fit, nullptr, nullptr, status, ws, static_cast<hipStream_t>(stream),
          false};
 
-  // forward: rows per lane K, rows per LDS tile R, individuals per block G
+  // forward: rows per lane K, rows per LDS tile R, individuals per group G
   const int Ks_f[2] = {8, 4};
-  const int Rs_f[5] = {256, 512, 1024, 2048, 4096};
-  const int Gs_f[5] = {4, 8, 16, 32, 64};
+  const int Rs_f[4] = {256, 512, 1024, 2048};
+  const int Gs_f[3] = {16, 32, 64};
   const int lds = lds_limit_bytes();
-  Tuned best_f{0, 0, 0, 0, 0};
+  Tuned best_f{0, 0, 0};
   float best_f_ms = 1e30f;
   TileCfg fc_best;
   for (int k : Ks_f) {
@@ -820,9 +782,9 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
       if (r < 64 * k) continue;
       for (int g : Gs_f) {
         if (forward_lds_bytes(F, r, g) > size_t(lds)) continue;
-        const Tuned t{k, r, g, 0, 0};
+        const Tuned t{k, r, g};
         const TileCfg fc = plan_forward(st, &t);
-        const AdjPlan ac = plan_adjoint(st, fc.D, nullptr, adj_span_cap(s));
+        const AdjPlan ac = plan_adjoint(st, nullptr, adj_span_cap(s));
         const float ms = time_plans(c, fc, ac, trials);
         if (ms < 0.0f) {
           const std::string why = last_error();
@@ -842,27 +804,24 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   int len = std::snprintf(desc, sizeof(desc), "forward K=%d R=%d G=%d (%.3f ms on %lld rows)", best_f.K,
                           best_f.R, best_f.G, double(best_f_ms), (long long)st.N);
 
-  if (with_grad) {
+  if (with_grad && C_max > 0) {
     c.with_grad = true;
     c.grad = grad;
-    // (K, NC) of the path tier, or (K, TC) of tier A without one (F = 0)
-    struct Cand {
-      int K, TC, F;
-    };
-    const Cand cands[9] = {{4, 0, 16}, {4, 0, 12}, {4, 0, 8}, {8, 0, 8}, {2, 0, 16},
-                           {2, 0, 32}, {4, 16, 0}, {2, 16, 0}, {2, 32, 0}};
-    const int Rs_a[5] = {256, 512, 768, 1024, 2048};
-    const int Gs_a[4] = {4, 8, 16, 32};
-    Tuned best_a{0, 0, 0, 0, 0};
+    // the path classes' tile R and group G, and which of classes 0-2 run two
+    // rows per lane (K mask; only the classes the shape can populate vary)
+    const int Rs_a[3] = {256, 512, 1024};
+    const int Gs_a[3] = {8, 16, 32};
+    const int kmasks[4] = {0, 4, 6, 7};  // class 2 first: its register array is the largest
+    Tuned best_a{-1, 0, 0};
     float best_a_ms = 1e30f;
-    for (const Cand& cd : cands) {
-      if (cd.F > 0 && C_max == 0) continue;
+    for (int km : kmasks) {
+      if ((km & 2) && C_max <= 4) continue;
+      if ((km & 4) && C_max <= 8) continue;
       for (int r : Rs_a) {
         for (int g : Gs_a) {
-          const Tuned t{cd.K, r, g, cd.TC, cd.F};
-          const AdjPlan ac = plan_adjoint(st, fc_best.D, &t, adj_span_cap(s));
-          const int lead_r = ac.nc_p > 0 ? ac.path.R : ac.reg.R;
-          if (lead_r != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
+          const Tuned t{km, r, g};
+          const AdjPlan ac = plan_adjoint(st, &t, adj_span_cap(s));
+          if (ac.R != r || !adjoint_plan_fits(st, ac)) continue;  // clamped: same as another
           const float ms = time_plans(c, fc_best, ac, trials);
           if (ms < 0.0f) {
             const std::string why = last_error();
@@ -875,11 +834,11 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
         }
       }
     }
-    if (best_a.K) {
+    if (best_a.K >= 0) {
       g_tuned_adj[tune_key(s, true)] = best_a;
       len += std::snprintf(desc + len, sizeof(desc) - size_t(len),
-                           "; fitness+gradient with adjoint K=%d TC=%d NC=%d R=%d G=%d (%.3f ms)",
-                           best_a.K, best_a.TC, best_a.F, best_a.R, best_a.G, double(best_a_ms));
+                           "; fitness+gradient with adjoint Kmask=%d R=%d G=%d (%.3f ms)", best_a.K, best_a.R,
+                           best_a.G, double(best_a_ms));
     }
   }
   if (cache_path) {

@@ -151,43 +151,80 @@ struct UopMem {
   __device__ inline uint2 at(int pc) const { return load_uop(p, pc); }
 };
 
-// UopRegs<NP>: the whole program held in VGPRs, lane l of register pair e
-// holding uop e*64 + l (NP*64 >= uops of the longest program); at() copies a
-// uop into SGPRs with v_readlane, so the interpreter loop touches no memory
-// for its instruction stream.  load() is a coalesced vector load (vmcnt, not
-// lgkmcnt), issued one individual ahead.
-template <int NP>
-struct UopRegs {
-  uint32_t lo[NP], hi[NP];
-  __device__ inline void load(const uint2* __restrict__ prog, int n) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int e = 0; e < NP; ++e) {
-      const int idx = e * 64 + lane;
-      uint2 u = make_uint2(UOP_END_HDR, 0u);
-      if (idx < n) u = prog[idx];
-      lo[e] = u.x;
-      hi[e] = u.y;
+// Lane-held window of a stream of 64-bit words (uops, flush events): lane l
+// holds word base + l.  One coalesced vector load (vmcnt, not lgkmcnt).  Words
+// at or past `n` read as `fill`.
+__device__ inline void load_window(const uint2* __restrict__ p, int base, int n, uint2 fill,
+                                   uint32_t& lo, uint32_t& hi) {
+  const int idx = base + int(threadIdx.x & 63);
+  uint2 u = fill;
+  if (idx < n) u = p[idx];
+  lo = u.x;
+  hi = u.y;
+}
+__device__ inline uint2 read_window(uint32_t lo, uint32_t hi, int l) {
+  return make_uint2(uint32_t(__builtin_amdgcn_readlane(int(lo), l)),
+                    uint32_t(__builtin_amdgcn_readlane(int(hi), l)));
+}
+
+// UopWin<ROLL>: the program held in VGPRs 64 uops at a time (lane l of the
+// current window holds uop 64w + l); at() copies a uop into SGPRs with
+// v_readlane, so the interpreter loop issues no memory access for its
+// instruction stream.  The first window is loaded one individual ahead by the
+// caller (load_window) and handed to begin().  ROLL (programs of more than 64
+// uops): entering a window loads the next one, which becomes current when the
+// program counter crosses into it 64 uops later, so its load latency is
+// hidden by the uops in between.  at() must be called with pc = 0, 1, 2, ...
+// in order (a forward sweep).
+template <bool ROLL>
+struct UopWin {
+  uint32_t lo = 0, hi = 0, nlo = 0, nhi = 0;
+  const uint2* __restrict__ p = nullptr;
+  int n = 0;  // words of the program's uop row that may be read
+  __device__ inline void begin(const uint2* __restrict__ prog, int n_words, uint32_t lo0, uint32_t hi0) {
+    lo = lo0;
+    hi = hi0;
+    if constexpr (ROLL) {
+      p = prog;
+      n = n_words;
+      if (n_words > 64) load_window(prog, 64, n_words, make_uint2(UOP_END_HDR, 0u), nlo, nhi);
     }
   }
-  __device__ inline uint2 at(int pc) const {
+  __device__ inline uint2 at(int pc) {
     const int l = pc & 63;
-    if constexpr (NP == 1) {
-      return make_uint2(uint32_t(__builtin_amdgcn_readlane(int(lo[0]), l)),
-                        uint32_t(__builtin_amdgcn_readlane(int(hi[0]), l)));
-    } else {
-      const int q = pc >> 6;
-      uint32_t a = UOP_END_HDR, b = 0u;
-#pragma unroll
-      for (int e = 0; e < NP; ++e) {
-        if (q == e) {
-          a = uint32_t(__builtin_amdgcn_readlane(int(lo[e]), l));
-          b = uint32_t(__builtin_amdgcn_readlane(int(hi[e]), l));
-          GG_BRANCH();
-        }
+    if constexpr (ROLL) {
+      if (l == 0 && pc != 0) {  // wave-uniform: crossing into the next window
+        lo = nlo;
+        hi = nhi;
+        if (pc + 64 < n) load_window(p, pc + 64, n, make_uint2(UOP_END_HDR, 0u), nlo, nhi);
+        GG_BRANCH();
       }
-      return make_uint2(a, b);
     }
+    return read_window(lo, hi, l);
+  }
+};
+
+// Flush events of path forward mode (one uint2 each), consumed in order: the
+// first 64 are lane-held (loaded one individual ahead, like a program's first
+// window); later windows are loaded when reached (few programs have more than
+// 64 events).
+struct EventWin {
+  uint32_t lo = 0, hi = 0;
+  const uint2* __restrict__ p = nullptr;
+  int n = 0;
+  __device__ inline void begin(const uint2* __restrict__ ev, int n_ev, uint32_t lo0, uint32_t hi0) {
+    lo = lo0;
+    hi = hi0;
+    p = ev;
+    n = n_ev;
+  }
+  __device__ inline uint2 at(int m) {
+    const int l = m & 63;
+    if (l == 0 && m != 0) {  // wave-uniform
+      load_window(p, m, n, make_uint2(0u, 0u), lo, hi);
+      GG_BRANCH();
+    }
+    return read_window(lo, hi, l);
   }
 };
 
@@ -257,7 +294,7 @@ __device__ inline void stage_y(double* yts, const float* __restrict__ y, int R, 
 }
 
 // Per-individual words (metadata, fit coefficients) fetched one individual
-// ahead, like UopRegs: lane w holds word w, a coalesced vector load.  Reading
+// ahead, like a program's first window: lane w holds word w, a coalesced vector load.  Reading
 // a word back (v_readlane) waits only for loads issued one individual ago,
 // where a scalar or vector load of the current individual's words, issued
 // after the next program's prefetch, would wait for that prefetch as well.
@@ -396,7 +433,7 @@ __device__ inline void op_value(uint32_t op, typename VecT<T, K>::type& acc,
 }
 
 // Evaluate the program on K rows per lane; returns the predictions.
-//   prog    uop source of this individual (UopMem or UopRegs)
+//   prog    uop source of this individual (UopMem or UopWin)
 //   xt      LDS row tile: feature k, row r at xt[k*rstride + r]
 //   lrow    this lane's first row within the tile (batch start + lane_row)
 //
@@ -405,7 +442,7 @@ __device__ inline void op_value(uint32_t op, typename VecT<T, K>::type& acc,
 // decision is a single-bit test of the header, the tests are nested (a uop
 // pays only for the path it takes) and the END test sits at the loop latch.
 template <typename T, int K, int D, class Src>
-__device__ inline typename VecT<T, K>::type run_program(const Src& prog,
+__device__ inline typename VecT<T, K>::type run_program(Src& prog,
                                                         const float* __restrict__ xt, int rstride,
                                                         int lrow) {
   using V = typename VecT<T, K>::type;

@@ -92,7 +92,19 @@ __device__ inline int xcd_item(int b, int total) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <typename T, int K, int D, int W, bool SSE, int NP>
+// Stack depth passes.  Most programs need at most 4 register stack slots
+// (a program needing s slots has at least 2^(s+1) leaves, so 5 or more occur
+// only from 127 tokens on).  A batch that may hold deeper programs runs two
+// launches: pass 1 with 4 slots skips the deep programs, pass 2 with 8 slots
+// evaluates only them (a block whose group has none exits before staging).
+enum : int { PASS_ALL = 0, PASS_SHALLOW = 1, PASS_DEEP = 2 };
+constexpr int kShallowSlots = 4;
+
+__device__ inline bool in_pass(int pass, int slots) {
+  return pass == PASS_ALL || (pass == PASS_SHALLOW ? slots <= kShallowSlots : slots > kShallowSlots);
+}
+
+template <typename T, int K, int D, int W, bool SSE, bool ROLL, int PASS>
 __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R = p.R;
@@ -107,15 +119,23 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
   const int Gn = min(p.G, p.M - ind0);
   const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
-  constexpr int BR = 64 * K;  // rows per batch
+  constexpr int BR = 64 * K;
 
+  if constexpr (PASS == PASS_DEEP) {  // block-uniform: nothing of this pass in the group
+    bool any = false;
+    for (int j = 0; j < Gn; ++j) any = any || p.meta[ind0 + j].slots > kShallowSlots;
+    if (!any) return;
+  }
   __shared__ int queue;
-  // status and mu of the group's individuals (G <= 64), read with the queue
-  // claim: one LDS round trip per individual, no global load on the way
+  // status (0 evaluate, else skip) and mu of the group's individuals (G <= 64),
+  // read with the queue claim: one LDS round trip per individual, no global load
   __shared__ uint2 gmeta[64];
   for (int j = threadIdx.x; j < Gn * 4; j += blockDim.x) accs[j] = 0.0;
-  for (int j = threadIdx.x; j < Gn; j += blockDim.x)
-    gmeta[j] = make_uint2(uint32_t(p.meta[ind0 + j].status), __float_as_uint(p.meta[ind0 + j].mu));
+  for (int j = threadIdx.x; j < Gn; j += blockDim.x) {
+    const ProgMeta& m = p.meta[ind0 + j];
+    const bool run = m.status == 0 && in_pass(PASS, m.slots);
+    gmeta[j] = make_uint2(run ? 0u : 1u, __float_as_uint(m.mu));
+  }
 
   const int64_t span_r0 = int64_t(span) * p.tiles_per_span * R;
   for (int tile = 0; tile < p.tiles_per_span; ++tile) {
@@ -131,22 +151,27 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     const int nbatch = (nvalid + BR - 1) / BR;
     // the waves claim the group's individuals from the tile's queue (a
     // wave-uniform loop, no cross-lane traffic under divergent control); the
-    // next individual is claimed and its program loaded while this one runs
-    UopRegs<NP> prog, prog_next;
+    // next individual is claimed and its first program window loaded while
+    // this one runs
+    uint32_t w0lo = 0, w0hi = 0, w1lo = 0, w1hi = 0;
+    const uint2 endu = make_uint2(UOP_END_HDR, 0u);
     int jj = claim_next(&queue);
-    if (jj < Gn) prog.load(p.uops + size_t(ind0 + jj) * p.U_stride, p.U_stride);
+    if (jj < Gn) load_window(p.uops + size_t(ind0 + jj) * p.U_stride, 0, p.U_stride, endu, w0lo, w0hi);
     while (jj < Gn) {
       const uint2 gm = gmeta[jj];
       const int jn = claim_next(&queue);
-      const int status = __builtin_amdgcn_readfirstlane(int(gm.x));
+      const int skip = __builtin_amdgcn_readfirstlane(int(gm.x));
       const float mu_f = __uint_as_float(__builtin_amdgcn_readfirstlane(int(gm.y)));
-      if (jn < Gn) prog_next.load(p.uops + size_t(ind0 + jn) * p.U_stride, p.U_stride);
-      if (status == 0) {
+      if (jn < Gn) load_window(p.uops + size_t(ind0 + jn) * p.U_stride, 0, p.U_stride, endu, w1lo, w1hi);
+      if (skip == 0) {
         const double mu = double(mu_f);
         const double emu = mu - ybar;
+        const uint2* prow = p.uops + size_t(ind0 + jj) * p.U_stride;
         Moments<SSE> m;
         for (int b = 0; b < nbatch; ++b) {
           const int lrow = b * BR + lane_row<K>(lane);
+          UopWin<ROLL> prog;
+          prog.begin(prow, p.U_stride, w0lo, w0hi);
           const auto v = run_program<T, K, D>(prog, xs, R, lrow);
           accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
         }
@@ -159,38 +184,42 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
         accs[jj * 4 + 2] += sc;
         accs[jj * 4 + 3] += se;
       }
-      prog = prog_next;
+      w0lo = w1lo;
+      w0hi = w1hi;
       jj = jn;
     }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < Gn * 4; j += blockDim.x) {
     const int jj = j >> 2, q = j & 3;
-    p.part[(size_t(ind0 + jj) * p.n_spans + span) * 4 + q] = accs[j];
+    if (gmeta[jj].x == 0u || PASS == PASS_ALL)
+      p.part[(size_t(ind0 + jj) * p.n_spans + span) * 4 + q] = accs[j];
   }
 }
 
-template <typename T, int K, int D, int W, int NP>
+template <typename T, int K, int D, int W, bool ROLL, int PASS>
 static hipError_t fused_impl(const TileCfg& c, const FwdParams& fp, bool sse, hipStream_t s) {
-  const size_t sh = size_t(fp.F) * fp.R * sizeof(float) + size_t(fp.R) * sizeof(double) +
-                    size_t(fp.G) * 4 * sizeof(double) + 16;
+  const size_t sh = forward_lds_bytes(fp.F, fp.R, fp.G);
   const int nb = c.n_spans * c.n_groups;
   if (sse)
-    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, true, NP>), dim3(nb), dim3(W * 64), sh, s, fp);
+    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, true, ROLL, PASS>), dim3(nb), dim3(W * 64), sh, s, fp);
   else
-    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, false, NP>), dim3(nb), dim3(W * 64), sh, s, fp);
+    hipLaunchKernelGGL((k_fused_fwd<T, K, D, W, false, ROLL, PASS>), dim3(nb), dim3(W * 64), sh, s, fp);
   return hipGetLastError();
 }
 
-template <typename T, int K, int D, int W>
-static hipError_t fused_np(const TileCfg& c, const FwdParams& fp, bool sse, hipStream_t s) {
-  switch (c.NP) {
-    case 1: return fused_impl<T, K, D, W, 1>(c, fp, sse, s);
-    case 2: return fused_impl<T, K, D, W, 2>(c, fp, sse, s);
-    case 4: return fused_impl<T, K, D, W, 4>(c, fp, sse, s);
-    case 8: return fused_impl<T, K, D, W, 8>(c, fp, sse, s);
-    default: return hipErrorInvalidValue;
-  }
+// Programs of up to 63 tokens (at most 64 uops with END) are held in one
+// window; longer ones roll.  A batch that may hold programs needing more than
+// four stack slots (127 tokens or more) runs the shallow and the deep pass.
+template <typename T, int K>
+static hipError_t fused_k(const TileCfg& c, const FwdParams& fp, bool sse, bool roll, bool deep_possible,
+                          hipStream_t s) {
+  hipError_t e;
+  if (!roll) return fused_impl<T, K, kShallowSlots, 4, false, PASS_ALL>(c, fp, sse, s);
+  if (!deep_possible) return fused_impl<T, K, kShallowSlots, 4, true, PASS_ALL>(c, fp, sse, s);
+  e = fused_impl<T, K, kShallowSlots, 4, true, PASS_SHALLOW>(c, fp, sse, s);
+  if (e != hipSuccess) return e;
+  return fused_impl<T, K, 8, 4, true, PASS_DEEP>(c, fp, sse, s);
 }
 
 hipError_t launch_fused_forward(bool fp64, const TileCfg& c, const uint2* uops, int U_stride,
@@ -198,14 +227,12 @@ hipError_t launch_fused_forward(bool fp64, const TileCfg& c, const uint2* uops, 
                                 const double* stats, double* part, bool want_sse, hipStream_t s) {
   FwdParams fp{uops, U_stride, meta, M, d.X, d.ldx, d.F, d.N, d.y, stats, part,
                c.R, c.G, c.n_groups, c.n_spans, c.tiles_per_span};
-  if (fp64) return fused_np<double, 4, 8, 4>(c, fp, want_sse, s);
-  if (c.D <= 4 && c.NP != 1) return hipErrorInvalidValue;
-  if (c.K == 4) {
-    if (c.D <= 4) return fused_impl<float, 4, 4, 4, 1>(c, fp, want_sse, s);
-    return fused_np<float, 4, 8, 4>(c, fp, want_sse, s);
-  }
-  if (c.D <= 4) return fused_impl<float, 8, 4, 4, 1>(c, fp, want_sse, s);
-  return fused_np<float, 8, 8, 4>(c, fp, want_sse, s);
+  const bool roll = U_stride > 64;               // L_max + 1 > 64 uops possible
+  const bool deep = U_stride - 2 >= 127;         // L_max >= 127: 5+ slots possible
+  if (fp64) return fused_k<double, 4>(c, fp, want_sse, roll, deep, s);
+  if (c.K == 4) return fused_k<float, 4>(c, fp, want_sse, roll, deep, s);
+  if (c.K == 8) return fused_k<float, 8>(c, fp, want_sse, roll, deep, s);
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ finalize
@@ -254,10 +281,16 @@ __device__ inline void finalize_one(double A, double B, double C, double E, doub
     aux4[2] = mse;
     aux4[3] = nmse;
   }
-  if (ab2) {  // seed of the adjoint: r = ab2[0] + ab2[1]*p - y, scale 2*ab2[1]/N
+  if (ab2) {  // seed of the adjoint: residual ab2[S0] + ab2[S1] p - y, scaled
     const bool ls = (flags & GPGOMEA_LINEAR_SCALING) != 0;
-    ab2[0] = ls ? a : 0.0;
-    ab2[1] = sts != 0 ? 0.0 : (ls ? b : 1.0);
+    ab2[AB_S0] = ls ? a : 0.0;
+    ab2[AB_S1] = sts != 0 ? 0.0 : (ls ? b : 1.0);
+    // 2^e with e the exponent of the RMS residual sqrt(f) (1 when f is 0 or
+    // not finite): the residuals divided by it are O(1) on average
+    int e = 0;
+    if (sts == 0 && f > 0.0 && isfinite(f)) (void)frexp(sqrt(f), &e);
+    ab2[AB_INV_SCALE] = ldexp(1.0, -e);
+    ab2[AB_SCALE] = ldexp(1.0, e);
   }
 }
 
@@ -291,7 +324,7 @@ __global__ __launch_bounds__(256) void k_finalize(const ProgMeta* __restrict__ m
   if (lane == 0)
     finalize_one(A, B, C, E, double(pm.mu), stats, flags, pm.status, fitness + i,
                  aux ? aux + size_t(i) * 4 : nullptr, status ? status + i : nullptr,
-                 ab ? ab + size_t(i) * 2 : nullptr);
+                 ab ? ab + size_t(i) * AB_WORDS : nullptr);
 }
 
 hipError_t launch_finalize(const ProgMeta* meta, int M, const double* part, int n_spans,
@@ -347,7 +380,8 @@ __global__ __launch_bounds__(W * 64) void k_plain_fwd(PlainParams p) {
       const int nbatch = (nvalid + BR - 1) / BR;
       for (int b = w; b < nbatch; b += W) {
         const int lrow = b * BR + lane_row<K>(lane);
-        const auto v = run_program<T, K, D>(UopMem{p.prog}, xs, R, lrow);
+        UopMem prog{p.prog};
+        const auto v = run_program<T, K, D>(prog, xs, R, lrow);
         accumulate<T, K, SSE>(m, v, yts, lrow, nvalid, mu, emu);
       }
     }
@@ -421,7 +455,7 @@ hipError_t launch_plain_forward(bool fp64, const TileCfg& c, int i, const uint2*
                  fitness + i,
                  aux ? aux + size_t(i) * 4 : nullptr,
                  status ? status + i : nullptr,
-                 ab ? ab + size_t(i) * 2 : nullptr,
+                 ab ? ab + size_t(i) * AB_WORDS : nullptr,
                  c.R};
   const bool sse = aux != nullptr || !(flags & GPGOMEA_LINEAR_SCALING);
   if (fp64) return plain_impl<double, 4, 8, 4>(c, pp, sse, s);

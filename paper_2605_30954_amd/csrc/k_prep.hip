@@ -141,19 +141,21 @@ __device__ inline int uop_cost(uint32_t op) {
   }
 }
 
-// Emits uops of one program; state lives in LDS, one active lane.
 // Path forward mode keeps, per constant j, an entry T[j]: the product of the
 // local partials from constant j up to the last point where its subtree was
 // folded into T ("flushed": at a merge, a uop whose two operands both hold
 // constants, and at the push of a value that holds constants).  The compile
-// step lists these flush events in uop order, one 32-bit descriptor each:
-//   side A [0:15): lo (7 bits) | n (7 bits) << 7 | assign << 14
-//   side S [15:30): the same for a merge's src operand (unused for a push)
+// step lists these flush events in uop order, one uint2 each (x: the acc side
+// of a merge or the pushed value, y: a merge's src side, 0 for a push); a
+// side is
+//   lo (9 bits) | n (9 bits) << 9 | assign << 18
 // where [lo, lo + n) is the operand's constant range (contiguous in postfix
 // order) and `assign` says the entry has never been written (a single
-// constant): T[lo] = f instead of T[e] *= f.  Ranges need nc <= 127.
+// constant): T[lo] = f instead of T[e] *= f.  A program of L tokens has at most
+// L - 1 events (one merge and one push per binary operator), so a row of
+// L_max events never overflows.
 __device__ inline uint32_t flush_side(int lo, int n, bool assign) {
-  return uint32_t(lo & 127) | (uint32_t(n & 127) << 7) | (assign ? 1u << 14 : 0u);
+  return uint32_t(lo & 511) | (uint32_t(n & 511) << 9) | (assign ? 1u << 18 : 0u);
 }
 
 // Emits uops of one program; state lives in LDS, one active lane.
@@ -161,7 +163,7 @@ struct Emitter {
   uint2* out;
   const float* cs;
   CompileLds* L;
-  uint32_t* events;  // flush events, in uop order
+  uint2* events;  // flush events, in uop order
   int event_cap = 0, n_event = 0;
   int n = 0, cap = 0, tape = 0, cost = 0;
   bool push_pending = false;
@@ -169,8 +171,9 @@ struct Emitter {
   int push_node = -1;  // the subtree pushed by the next uop
   bool bad = false;
 
-  __device__ inline void event(uint32_t d) {
-    if (n_event < event_cap) events[n_event] = d;
+  __device__ inline void event(uint32_t a, uint32_t s) {
+    if (n_event < event_cap) events[n_event] = make_uint2(a, s);
+    else bad = true;  // cannot happen (event_cap >= L_max - 1); never drop one silently
     ++n_event;
   }
   __device__ inline void emit(uint32_t hdr, uint32_t payload) {
@@ -180,7 +183,7 @@ struct Emitter {
       const bool hc = L->hasc[pn] != 0;
       hdr = with_push(hdr, push_slot, hc);
       if (hc) {  // the pushed value's pending factor is folded into T
-        event(flush_side(L->clo[pn], L->cnum[pn], !L->written[pn]));
+        event(flush_side(L->clo[pn], L->cnum[pn], !L->written[pn]), 0u);
         L->written[pn] = 1;
       }
       push_pending = false;
@@ -196,8 +199,8 @@ struct Emitter {
   // the uop just emitted merges operand subtree a (acc) and b (src), both
   // holding constants; the result's entries are all written
   __device__ inline void merge(int a, int b) {
-    event(flush_side(L->clo[a], L->cnum[a], !L->written[a]) |
-          (flush_side(L->clo[b], L->cnum[b], !L->written[b]) << 15));
+    event(flush_side(L->clo[a], L->cnum[a], !L->written[a]),
+          flush_side(L->clo[b], L->cnum[b], !L->written[b]));
   }
 };
 
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
                                                  const float* __restrict__ consts, int C_max, int F,
                                                  int Dmax, int U_stride, uint2* __restrict__ uops,
                                                  ProgMeta* __restrict__ meta,
-                                                 uint32_t* __restrict__ merges, int MT) {
+                                                 uint2* __restrict__ events, int ET) {
   __shared__ CompileLds smem[4];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + w;
@@ -299,8 +302,8 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
   E.out = out;
   E.cs = cs;
   E.L = &L;
-  E.events = merges + size_t(i) * MT;
-  E.event_cap = MT;
+  E.events = events + size_t(i) * ET;
+  E.event_cap = ET;
   E.cap = U_stride - 2;
   int maxsp = 0;
   if (!bad) {
@@ -451,18 +454,19 @@ __global__ __launch_bounds__(256) void k_compile(const int8_t* __restrict__ ops,
 
 hipError_t launch_compile(const int8_t* ops, int M, int L_max, const float* consts, int C_max,
                           int F, int Dmax, int U_stride, uint2* uops, ProgMeta* meta,
-                          uint32_t* merges, int MT, hipStream_t s) {
+                          uint2* events, int ET, hipStream_t s) {
   const int nb = (M + 3) / 4;
   hipLaunchKernelGGL(k_compile, dim3(nb), dim3(256), 0, s, ops, M, L_max, consts, C_max, F, Dmax,
-                     U_stride, uops, meta, merges, MT);
+                     U_stride, uops, meta, events, ET);
   return hipGetLastError();
 }
 
 // -------------------------------------------------------------------- probe
 // One wave per individual; the block stages the first 64*K rows of X in LDS.
-// The program is read into registers with one coalesced load (NP register
-// pairs), so the uop stream costs no memory round trip per uop.
-template <typename T, int K, int D, int NP>
+// The program is read into registers 64 uops at a time (coalesced loads), so
+// the uop stream costs no memory round trip per uop.  Eight stack slots: the
+// probe evaluates every program, whatever its depth.
+template <typename T, int K, int D, bool ROLL>
 __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, int U_stride,
                                                ProgMeta* __restrict__ meta, int M,
                                                const float* __restrict__ X, int64_t ldx, int F,
@@ -479,8 +483,11 @@ __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, i
   const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + w);
   if (i >= M) return;
   if (meta[i].status != 0) return;
-  UopRegs<NP> prog;
-  prog.load(uops + size_t(i) * U_stride, U_stride);
+  const uint2* prow = uops + size_t(i) * U_stride;
+  uint32_t lo, hi;
+  load_window(prow, 0, U_stride, make_uint2(UOP_END_HDR, 0u), lo, hi);
+  UopWin<ROLL> prog;
+  prog.begin(prow, U_stride, lo, hi);
   const auto p = run_program<T, K, D>(prog, xs, R, lane_row<K>(lane));
   float s = 0.0f;
 #pragma unroll
@@ -493,34 +500,22 @@ __global__ __launch_bounds__(256) void k_probe(const uint2* __restrict__ uops, i
   if (lane == 0) meta[i].mu = isfinite(mu) ? mu : 0.0f;
 }
 
-template <typename T, int K, int D, int NP>
+template <typename T, int K, int D, bool ROLL>
 static hipError_t probe_impl(const uint2* uops, int U_stride, ProgMeta* meta, int M,
                              const DataArgs& d, hipStream_t s) {
   const size_t sh = size_t(d.F) * 64 * K * sizeof(float);
-  hipLaunchKernelGGL((k_probe<T, K, D, NP>), dim3((M + 3) / 4), dim3(256), sh, s, uops, U_stride,
+  hipLaunchKernelGGL((k_probe<T, K, D, ROLL>), dim3((M + 3) / 4), dim3(256), sh, s, uops, U_stride,
                      meta, M, d.X, d.ldx, d.F, d.N);
   return hipGetLastError();
 }
 
-template <typename T, int D>
-static hipError_t probe_np(int NP, const uint2* uops, int U_stride, ProgMeta* meta, int M,
-                           const DataArgs& d, hipStream_t s) {
-  switch (NP) {
-    case 1: return probe_impl<T, 4, D, 1>(uops, U_stride, meta, M, d, s);
-    case 2: return probe_impl<T, 4, D, 2>(uops, U_stride, meta, M, d, s);
-    case 4: return probe_impl<T, 4, D, 4>(uops, U_stride, meta, M, d, s);
-    case 8: return probe_impl<T, 4, D, 8>(uops, U_stride, meta, M, d, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_probe(bool fp64, int K, int D, const uint2* uops, int U_stride, ProgMeta* meta,
-                        int M, const DataArgs& d, hipStream_t s) {
-  (void)K;
-  const int NP = uop_pairs(U_stride - 2);  // U_stride = L_max + 2; at most L_max + 1 uops
-  if (fp64) return probe_np<double, 8>(NP, uops, U_stride, meta, M, d, s);
-  if (D <= 4 && NP == 1) return probe_impl<float, 4, 4, 1>(uops, U_stride, meta, M, d, s);
-  return probe_np<float, 8>(NP, uops, U_stride, meta, M, d, s);
+hipError_t launch_probe(bool fp64, const uint2* uops, int U_stride, ProgMeta* meta, int M,
+                        const DataArgs& d, hipStream_t s) {
+  const bool roll = U_stride > 64;  // programs of more than 64 uops possible
+  if (fp64) return roll ? probe_impl<double, 4, 8, true>(uops, U_stride, meta, M, d, s)
+                        : probe_impl<double, 4, 8, false>(uops, U_stride, meta, M, d, s);
+  return roll ? probe_impl<float, 4, 8, true>(uops, U_stride, meta, M, d, s)
+              : probe_impl<float, 4, 8, false>(uops, U_stride, meta, M, d, s);
 }
 
 int lds_limit_bytes() {

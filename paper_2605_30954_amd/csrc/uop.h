@@ -140,12 +140,6 @@ __host__ __device__ constexpr inline int tape_src(uint32_t h) {
              : 0;
 }
 
-// VGPR pairs that hold a program of up to L_max tokens in registers (at most
-// L_max + 1 uops including END; lane l of pair e holds uop e*64 + l).
-__host__ __device__ constexpr inline int uop_pairs(int L_max) {
-  return L_max + 1 <= 64 ? 1 : L_max + 1 <= 128 ? 2 : L_max + 1 <= 256 ? 4 : 8;
-}
-
 // Per-individual metadata written by the compile kernel.
 struct ProgMeta {
   int32_t n_uops;   // including the END uop

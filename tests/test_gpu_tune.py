@@ -21,7 +21,7 @@ def test_autotune_then_parity(tmp_path):
     path = tmp_path / "tune.json"
     desc = gg.autotune(ops, cs, X, y, with_grad=True, cache_path=str(path), trials=1)
     log(f"[tune] {desc}")
-    assert desc.startswith("forward K=") and "adjoint K=" in desc
+    assert desc.startswith("forward K=") and "adjoint Kmask=" in desc
     assert gg.load_tuning(str(path)) >= 2
     fit, grad, st = gg.grad_consts(ops, cs, X, y, return_status=True)
     fit, grad, st = fit.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
