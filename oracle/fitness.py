@@ -39,8 +39,10 @@ def target_stats(y):
     return ybar, vy
 
 
-def score(p, y, linear_scaling: bool = True):
-    """dict(fitness, a, b, mse, nmse, status, vp, pbar) for predictions p."""
+def score(p, y, linear_scaling: bool = True, degenerate_rtol: float = DEGENERATE_RTOL):
+    """dict(fitness, a, b, mse, nmse, status, vp, pbar) for predictions p.
+    ``degenerate_rtol`` is the threshold of the degenerate case (moved only by
+    the conditioning check)."""
     p = np.asarray(p, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     N = y.size
@@ -53,7 +55,7 @@ def score(p, y, linear_scaling: bool = True):
     dp = p - pbar
     spp = _sum(dp * dp)
     vp = spp / N
-    if vp <= DEGENERATE_RTOL * max(pbar * pbar, 1e-300):
+    if vp <= degenerate_rtol * max(pbar * pbar, 1e-300):
         a, b = ybar, 0.0
         ls = vy
     else:

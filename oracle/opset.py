@@ -63,13 +63,16 @@ def to_range(v, rng: str):
     return v
 
 
-def _clamp(t):
+def _clamp(t, clamp=CLAMP):
     # NaN compares false on both sides and is passed through unchanged
-    return np.where(t < -CLAMP, -CLAMP, np.where(t > CLAMP, CLAMP, t))
+    return np.where(t < -clamp, -clamp, np.where(t > clamp, clamp, t))
 
 
-def apply(op: int, a, b=None):
-    """Value of operator ``op`` on float64 arrays (same shape)."""
+def apply(op: int, a, b=None, guard=GUARD, clamp=CLAMP):
+    """Value of operator ``op`` on float64 arrays (same shape).  ``guard`` and
+    ``clamp`` default to the protection thresholds; other values serve only
+    the conditioning check (mca), which moves them to find the decisions an
+    input sits next to."""
     with np.errstate(all="ignore"):
         if op == ADD:
             return a + b
@@ -78,7 +81,7 @@ def apply(op: int, a, b=None):
         if op == MUL:
             return a * b
         if op == DIV:
-            g = np.abs(b) < GUARD
+            g = np.abs(b) < guard
             return np.where(g, 1.0, a / np.where(g, 1.0, b))
         if op == SIN:
             return np.sin(a)
@@ -89,18 +92,18 @@ def apply(op: int, a, b=None):
         if op == SQRT:
             return np.sqrt(np.abs(a))
         if op == EXP:
-            return np.exp(_clamp(a))
+            return np.exp(_clamp(a, clamp))
         if op == LOG:
-            g = np.abs(a) < GUARD
+            g = np.abs(a) < guard
             return np.where(g, 0.0, np.log(np.where(g, 1.0, np.abs(a))))
         if op == POW:
-            g = np.abs(a) < GUARD
+            g = np.abs(a) < guard
             t = b * np.log(np.where(g, 1.0, np.abs(a)))
-            return np.where(g, 0.0, np.exp(_clamp(t)))
+            return np.where(g, 0.0, np.exp(_clamp(t, clamp)))
     raise ValueError(f"not an operator: {op}")
 
 
-def partials(op: int, a, b, v):
+def partials(op: int, a, b, v, guard=GUARD, clamp=CLAMP):
     """(d v / d a, d v / d b) of ``v = apply(op, a, b)``; b-partial is None
     for unary operators.  A guarded branch or a clamp in its saturated range
     has derivative 0; sqrt(|a|) has derivative sign(a)/(2 sqrt|a|), taken as 0
@@ -114,7 +117,7 @@ def partials(op: int, a, b, v):
         if op == MUL:
             return b, a
         if op == DIV:
-            g = np.abs(b) < GUARD
+            g = np.abs(b) < guard
             bs = np.where(g, 1.0, b)
             return np.where(g, 0.0, 1.0 / bs), np.where(g, 0.0, -a / (bs * bs))
         if op == SIN:
@@ -127,16 +130,16 @@ def partials(op: int, a, b, v):
             r = np.sqrt(np.abs(a))
             return np.where(a == 0, 0.0, np.sign(a) / (2.0 * np.where(a == 0, 1.0, r))), None
         if op == EXP:
-            inside = (a >= -CLAMP) & (a <= CLAMP)
+            inside = (a >= -clamp) & (a <= clamp)
             return np.where(inside, np.exp(np.where(inside, a, 0.0)), 0.0), None
         if op == LOG:
-            g = np.abs(a) < GUARD
+            g = np.abs(a) < guard
             return np.where(g, 0.0, 1.0 / np.where(g, 1.0, a)), None
         if op == POW:
-            g = np.abs(a) < GUARD
+            g = np.abs(a) < guard
             la = np.log(np.where(g, 1.0, np.abs(a)))
             t = b * la
-            live = (~g) & (t >= -CLAMP) & (t <= CLAMP)
+            live = (~g) & (t >= -clamp) & (t <= clamp)
             r = np.exp(np.where(live, t, 0.0))
             da = np.where(live, r * b / np.where(g, 1.0, a), 0.0)
             db = np.where(live, r * la, 0.0)
@@ -144,18 +147,18 @@ def partials(op: int, a, b, v):
     raise ValueError(f"not an operator: {op}")
 
 
-def decision_inputs(op: int, a, b):
+def decision_inputs(op: int, a, b, guard=GUARD, clamp=CLAMP):
     """Inputs of the discrete decisions an operator takes, with thresholds:
     a list of (array, threshold) pairs compared as |array| vs threshold."""
     with np.errstate(all="ignore"):
         if op == DIV:
-            return [(b, GUARD)]
+            return [(b, guard)]
         if op == LOG:
-            return [(a, GUARD)]
+            return [(a, guard)]
         if op == EXP:
-            return [(a, CLAMP)]
+            return [(a, clamp)]
         if op == POW:
-            g = np.abs(a) < GUARD
+            g = np.abs(a) < guard
             t = b * np.log(np.where(g, 1.0, np.abs(a)))
-            return [(a, GUARD), (np.where(g, 0.0, t), CLAMP)]
+            return [(a, guard), (np.where(g, 0.0, t), clamp)]
     return []

@@ -72,6 +72,8 @@ class Evaluator:
               u ~ U(-1, 1) per row (Monte-Carlo arithmetic)
     record    a list; every decision input (guard / clamp / overflow) is
               appended as (array, threshold)
+    thresholds (guard, clamp) of the protected operators (the defaults of
+              opset; the conditioning check moves them)
     duals     if True also return d value / d constant for every active
               constant, shape [C, N], constants in post-order.  The chain
               rule's products absorb zeros: a local partial of exactly 0 (a
@@ -81,8 +83,10 @@ class Evaluator:
               above it); elsewhere the product is the plain one
     """
 
-    def __init__(self, X, rng="f32", perturb=None, record=None, duals=False):
+    def __init__(self, X, rng="f32", perturb=None, record=None, duals=False,
+                 thresholds=(O.GUARD, O.CLAMP)):
         self.X = X
+        self.guard, self.clamp = thresholds
         self.N = X.shape[1]
         self.rng = rng
         self.perturb = perturb
@@ -117,12 +121,12 @@ class Evaluator:
             raise ValueError(f"slot {i}: bad symbol {g}")
         a, da = self._ev(2 * i + 1)
         b, db = self._ev(2 * i + 2) if k == 2 else (None, None)
-        v = O.apply(g, a, b)
+        v = O.apply(g, a, b, self.guard, self.clamp)
         if self.record is not None:
-            self.record.extend(O.decision_inputs(g, a, b))
+            self.record.extend(O.decision_inputs(g, a, b, self.guard, self.clamp))
         d = None
         if self.duals and (da is not None or db is not None):
-            pa, pb = O.partials(g, a, b, v)
+            pa, pb = O.partials(g, a, b, v, self.guard, self.clamp)
             with np.errstate(all="ignore"):
                 if da is not None:
                     d = _chain(pa[None, :], da)
