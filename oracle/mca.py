@@ -20,6 +20,7 @@ Per individual, ``sensitivity`` reports
   * fit_spread: the largest |f_k - f_0| over those n + 2 runs (inf if a run's
     status differs from the unperturbed one: then either status is possible);
   * grad_spread: the same for the gradient in the max norm (with_grad);
+  * a_spread, b_spread: the same for the linear-scaling intercept and slope;
   * flipped: a discrete decision (guard, clamp, overflow, degenerate fit,
     finiteness) differed between runs;
   * near: a decision input lies within `window` (relative) of its threshold.
@@ -89,8 +90,8 @@ def sensitivity(genes, gconst, heights, X, y, precision="f32", n=8, seed=0,
             if with_grad else None
         d0 = _decisions(rec)
         info = dict(fitness=s0["fitness"], status=s0["status"], fit_spread=0.0,
-                    grad_spread=0.0 if with_grad else None, flipped=False,
-                    near=_near(rec, window))
+                    grad_spread=0.0 if with_grad else None, a_spread=0.0, b_spread=0.0,
+                    flipped=False, near=_near(rec, window))
         if s0["status"] == 0 and s0["vp"] <= 1e2 * FT.DEGENERATE_RTOL * max(s0["pbar"] ** 2, 1e-300) \
                 and s0["vp"] > 0:
             info["near"] = True
@@ -110,7 +111,7 @@ def sensitivity(genes, gconst, heights, X, y, precision="f32", n=8, seed=0,
             sk = FT.score(pk, y64, linear_scaling, degenerate_rtol=drt)
             if sk["status"] != s0["status"]:
                 info["flipped"] = True
-                info["fit_spread"] = np.inf
+                info["fit_spread"] = info["a_spread"] = info["b_spread"] = np.inf
                 if with_grad:
                     info["grad_spread"] = np.inf
                 continue
@@ -121,6 +122,8 @@ def sensitivity(genes, gconst, heights, X, y, precision="f32", n=8, seed=0,
             if s0["status"] != 0:
                 continue
             info["fit_spread"] = max(info["fit_spread"], abs(sk["fitness"] - s0["fitness"]))
+            info["a_spread"] = max(info["a_spread"], abs(sk["a"] - s0["a"]))
+            info["b_spread"] = max(info["b_spread"], abs(sk["b"] - s0["b"]))
             if with_grad and g0.size:
                 gk = _gradient(rk[1], pk, sk, y64, linear_scaling)
                 info["grad_spread"] = max(info["grad_spread"], float(np.max(np.abs(gk - g0))))

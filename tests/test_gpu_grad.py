@@ -29,7 +29,7 @@ def run_grad(cid, M, N, linear_scaling=True, plain=False, salt=1, min_gated=None
     gate_fitness(fit, st, ref, fl, vy, "f32", f"grad-call fitness cfg{cid}")
     refs = oracle_gradients(d, idx, linear_scaling)
     rep = gate_gradients(grad, st, refs, fl, vy, what=f"cfg{cid} ls={linear_scaling} plain={plain}")
-    assert rep["gated"] >= min_gated
+    assert rep["compared"] >= min_gated
     # per-row partials are float32: a gradient may be non-finite only where a
     # true per-row partial comes within a few decades of the float32 range
     nonfin = [m for m in range(M) if st[m] == 0 and not np.all(np.isfinite(grad[m]))]
@@ -59,10 +59,10 @@ def test_gradients_tiny_batches(M):
 
 
 def test_cfg5_gradients_full_operator_set():
-    # most random height-7 programs over all 11 operators have gradients that a
-    # one-ulp perturbation of the node values moves by more than the gate: they
-    # are flagged, so a larger sample keeps enough gateable individuals
-    run_grad(5, 64, 3001, min_gated=10)
+    # many random height-7 programs over all 11 operators have gradients that a
+    # one-ulp perturbation of the node values moves by more than the plain
+    # gate: their tolerance includes that measured spread
+    run_grad(5, 64, 3001, min_gated=32)
 
 
 def test_plain_adjoint_matches_fused():
@@ -86,24 +86,29 @@ def test_plain_adjoint_matches_fused():
     for what, g, st in (("fused", g1, s1), ("plain", g2, s2)):
         g, st = g.cpu().numpy(), st.cpu().numpy()
         rep = gate_gradients(g, st, refs, fl, vy, what=f"cfg4 {what}")
-        assert rep["gated"] >= 6
+        assert rep["compared"] >= 16
         nonfin = [m for m in range(M) if st[m] == 0 and not np.all(np.isfinite(g[m]))]
         assert all(partial_peak(d, m) >= 1e30 for m in nonfin), (what, nonfin)
 
 
 def test_gradient_against_central_differences():
     """GPU gradient vs FP64 central differences (h = 1e-4) of the oracle's
-    fitness; constants next to a kink (FD at h and h/2 disagree) are skipped."""
+    fitness, for every individual whose status is 0; constants next to a kink
+    (FD at h and h/2 disagree) are skipped.  The tolerance adds the binary32
+    rounding of the gradient's terms and its measured sensitivity, as the
+    parity gate does."""
     cfg = get_config(4)
     d = make_inputs(cfg, 24, 6000, salt=9)
     ops, cs, X, y = to_device(d)
     fit, grad, st = gg.grad_consts(ops, cs, X, y, return_status=True)
     grad = grad.cpu().numpy()
-    fl = oracle_flags(d, range(24), "f32", with_grad=True)
     vy = float(np.var(d["y"].astype(np.float64)))
+    sens = oracle_flags(d, list(range(24)), "f32", with_grad=True)
+    refs = oracle_gradients(d, list(range(24)))
     checked = 0
     for m in range(24):
-        if fl[m] or st[m].item() != 0:
+        gs = sens[m]["grad_spread"]
+        if st[m].item() != 0 or gs is None or not np.isfinite(gs):
             continue
         f1 = OG.fd_gradient(d["genes"][m], d["gc"][m], 5, d["X"], d["y"], h=1e-4)
         f2 = OG.fd_gradient(d["genes"][m], d["gc"][m], 5, d["X"], d["y"], h=5e-5)
@@ -112,10 +117,11 @@ def test_gradient_against_central_differences():
         sc = float(np.max(np.abs(f1)))
         if np.max(np.abs(f1 - f2)) > 1e-6 * sc + 1e-12 * vy:
             continue
-        assert np.max(np.abs(grad[m, : f1.size] - f1)) <= 2e-5 * sc + 1e-10 * vy, m
+        tol = 2e-5 * sc + 1e-10 * vy + 4 * 2.0 ** -24 * float(np.max(refs[m][0]["gabs"])) + 3 * gs
+        assert np.max(np.abs(grad[m, : f1.size] - f1)) <= tol, m
         checked += 1
     log(f"[fd] checked {checked} of 24")
-    assert checked >= 8
+    assert checked >= 12
 
 
 def test_autograd_function():

@@ -30,4 +30,4 @@ def test_autotune_then_parity(tmp_path):
     fl = oracle_flags(d, idx, "f32", with_grad=True)
     gate_fitness(fit, st, oracle_scores(d, idx), fl, vy, "f32", "tuned cfg2")
     rep = gate_gradients(grad, st, oracle_gradients(d, idx), fl, vy, what="tuned cfg2")
-    assert rep["gated"] >= M // 3
+    assert rep["compared"] >= M // 2

@@ -121,3 +121,18 @@ def test_threshold_shift_takes_the_other_decision(impl):
     X[1, 3] = np.float32(1.5)
     s = impl.sensitivity(g[None], gc[None], 4, X, y, n=2, window=1e-4)[0]
     assert not s["near"] and not s["flipped"] and s["fit_spread"] < 1e-5 * s["fitness"]
+
+
+def test_slope_spread_shows_a_variance_lost_against_the_mean():
+    """b = S_py / S_pp: with p = x0 + 1e4 the binary32 rounding of p is about
+    1e4 * 2^-24 of std(p), so the slope is known only to a few parts in 1e4;
+    with p = x0 it is known to about the unit roundoff."""
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (2, 3000)).astype(np.float32)
+    y = (2 * X[0] + 0.1 * X[1]).astype(np.float32)
+    progs = [([V0], []), ([V0, C, O.ADD], [1e4])]
+    gs, cs = zip(*[genotype(t, c) for t, c in progs])
+    sens = mca.sensitivity(np.stack(gs), np.stack(cs), 4, X, y, n=6)
+    b = [abs(s["b_spread"]) for s in sens]
+    assert b[0] < 1e-6 * 2.0 and 1e-5 * 2.0 < b[1] < 1e-2 * 2.0
+    assert sens[1]["a_spread"] > 1e4 * sens[1]["b_spread"] / 10   # a = ybar - b pbar
