@@ -10,12 +10,17 @@ the evaluation runs in the library's HIP kernels.
     ops, consts, lens, nconst = encode(genes, gene_consts, heights, L_max, C_max)
 """
 import ctypes
+import os
 
 import numpy as np
 
 from . import _lib
 from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  # noqa: F401
                    MAX_LEN, MAX_CONSTS, MAX_FEATURES, check, last_error, lib)
+
+#: launch shapes chosen by the autotuner on MI355X for the workloads of this
+#: repository (load with load_tuning(); the library never reads it by itself)
+TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
 __all__ = ["eval_batch", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
            "autotune", "load_tuning", "clear_graphs", "graph_count", "flags_of", "profile",
@@ -174,8 +179,9 @@ def autotune(ops, consts, X, y, linear_scaling=True, with_grad=False, cache_path
     return desc.value.decode()
 
 
-def load_tuning(cache_path):
-    """Load a tuning file written by autotune; returns the number of entries."""
+def load_tuning(cache_path=TUNING_FILE):
+    """Load a tuning file written by autotune (by default the shipped MI355X
+    one); returns the number of entries."""
     n = lib.gpgomea_load_tuning(str(cache_path).encode())
     if n < 0:
         raise LibraryError(n, last_error())
