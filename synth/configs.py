@@ -29,6 +29,36 @@ def _t_cfg5(x):
     return x[0] * x[1] * x[2] / (x[3] * (x[4] - x[5]) ** 2) * (1.0 + np.cos(x[6] * x[7] / x[8]))
 
 
+# The formula ladder of the paper's Experiment III (Tab. 1): expressions of
+# increasing difficulty that end in Feynman I.9.18 ("Squaring").
+def _t_addition(x):
+    return x[0] + x[1] + x[2] + x[3] + x[4] + x[5] + x[6] + x[7] + x[8]
+
+
+def _t_division(x):
+    return (x[0] + x[1] + x[2]) / (x[3] + x[4] + x[5] + x[6] + x[7] + x[8])
+
+
+def _t_subtraction(x):
+    return (x[0] + x[1] + x[2]) / (x[4] - x[3] + x[6] - x[5] + x[8] - x[7])
+
+
+def _t_multiplication(x):
+    return x[0] * x[1] * x[2] / (x[4] - x[3] + x[6] - x[5] + x[8] - x[7])
+
+
+def _t_squaring(x):
+    return x[0] * x[1] * x[2] / ((x[4] - x[3]) ** 2 + (x[6] - x[5]) ** 2 + (x[8] - x[7]) ** 2)
+
+
+def _den_diffs(x):
+    return x[4] - x[3] + x[6] - x[5] + x[8] - x[7]
+
+
+def _den_squares(x):
+    return (x[4] - x[3]) ** 2 + (x[6] - x[5]) ** 2 + (x[8] - x[7]) ** 2
+
+
 @dataclass(frozen=True)
 class Config:
     cid: int
@@ -47,6 +77,8 @@ class Config:
     erc_hi: float = 1.0
     variant_frac: float = 0.0     # share of GOM-style offspring in the batch
     description: str = ""
+    den: Callable = field(default=None, repr=False)  # the target's denominator, if any
+    den_min: float = 0.0          # rows with |den(x)| below this are redrawn
 
     @property
     def h_max(self) -> int:
@@ -76,6 +108,30 @@ CONFIGS = {
     5: Config(5, "cfg5-large-template", 8192, (7,), S.FUNCS_ALL, 9, 10_000_000, "U", 1.0, 5.0, _t_cfg5,
               description="8192 x h7 (255 nodes), 11 ops, F=9 U(1,5), N=1e7"),
 }
+
+# Experiment III's datasets (Tab. 1: 100,000 rows, 9 features) with its
+# operator set and template depth 6 (Tab. 2; depth 8 is the other setting) and
+# its smaller population, 2,000.  The paper does not give the x distribution:
+# U(1, 5) as for the large-template workload, with rows whose denominator is
+# within 0.01 of zero redrawn.  Without that, Subtraction's and Multiplication's
+# denominators (a sum of three differences) come arbitrarily close to zero:
+# the target is then set by a handful of near-singular rows, binary32
+# evaluation of the exact formula misses the NMSE <= 1e-6 success threshold
+# there, and a row below the division guard makes the formula itself wrong.
+_LADDER_ROWS = [
+    (6, "addition", "Addition", _t_addition, None),
+    (7, "division", "Division", _t_division, None),
+    (8, "subtraction", "Subtraction", _t_subtraction, _den_diffs),
+    (9, "multiplication", "Multiplication", _t_multiplication, _den_diffs),
+    (10, "squaring", "Squaring (Feynman I.9.18)", _t_squaring, _den_squares),
+]
+LADDER = {
+    cid: Config(cid, f"ladder-{name}", 2000, (6,), S.FUNCS_LADDER, 9, 100_000, "U", 1.0, 5.0, fn,
+                den=den, den_min=0.01 if den else 0.0,
+                description=f"Exp. III {title}: 2000 x h6, {{+,-,*,/,sq,sqrt}}, F=9 U(1,5), N=1e5")
+    for cid, name, title, fn, den in _LADDER_ROWS
+}
+CONFIGS.update(LADDER)
 
 
 def get_config(cid: int) -> Config:

@@ -35,10 +35,18 @@ def make_dataset(cfg: Config, N: int = None, salt: int = 0):
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         y64 = cfg.target(xr)
     # a row whose target is not a finite float32 (e.g. a division by an exact
-    # zero of the rounded inputs) is redrawn from its own stream; other rows
-    # keep their values
+    # zero of the rounded inputs), or whose denominator is closer to zero than
+    # the workload allows, is redrawn from its own stream; other rows keep
+    # their values
     redraw = rng_for(cfg.cid, STREAM_REDRAW, salt)
-    bad = ~(np.abs(y64) <= F32_MAX)
+
+    def rejected(xs, ys):
+        out = ~(np.abs(ys) <= F32_MAX)
+        if cfg.den is not None:
+            out |= ~(np.abs(cfg.den(xs)) >= cfg.den_min)
+        return out
+
+    bad = rejected(xr, y64)
     while np.any(bad):
         cols = np.nonzero(bad)[0]
         if cfg.x_dist == "N":
@@ -49,7 +57,8 @@ def make_dataset(cfg: Config, N: int = None, salt: int = 0):
         xr[:, cols] = X32[:, cols].astype(np.float64)
         with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
             y64[cols] = cfg.target(xr[:, cols])
-        bad = ~(np.abs(y64) <= F32_MAX)
+        bad = np.zeros(N, dtype=bool)
+        bad[cols] = rejected(xr[:, cols], y64[cols])
     if cfg.noise:
         y64 = y64 + cfg.noise * rng_for(cfg.cid, STREAM_NOISE, salt).standard_normal(N)
     y32 = y64.astype(np.float32)
