@@ -12,14 +12,16 @@
  *   App. A.2 notes the paper's GPU path lacks it), with NMSE = fitness/Var(y)
  *   (Eq. 2, population variance).  gpgomea_grad_consts adds the gradient of
  *   that fitness with respect to every constant of every individual (path
- *   forward mode over the tree's root-to-constant paths; not in the paper).  The batch is the set of changed
- *   offspring that Alg. 1 collects before its single Evaluate call.
+ *   forward mode over the tree's root-to-constant paths; not in the paper).
+ *   The batch is the set of changed offspring that Alg. 1 collects before its
+ *   single Evaluate call.
  *
  * Conventions common to all entry points
  *   - Every pointer named "device" is GPU memory owned by the caller.  The
  *     library never allocates device memory and never reads device data on
  *     the host.  Scratch space is the caller's `workspace` buffer, of at least
- *     gpgomea_workspace_bytes(...) bytes, 256-byte aligned.
+ *     gpgomea_workspace_bytes(...) bytes, 256-byte aligned (the no-allocation
+ *     entry point uses a static device array of the library instead).
  *   - `stream` is a hipStream_t (NULL = the default stream).  GPU entry points
  *     only enqueue work and return; outputs are valid after the stream has
  *     reached that point.  Inputs and the workspace must stay alive and
@@ -103,6 +105,28 @@ int gpgomea_eval_batch(const int8_t* ops, int32_t M, int32_t L_max, const float*
                        int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
                        const float* y, uint32_t flags, double* fitness, double* aux,
                        int8_t* status, void* workspace, size_t workspace_bytes, void* stream);
+
+/* No-allocation variant of gpgomea_eval_batch, for callers that cannot
+ * allocate device memory or create library objects while they run: code
+ * inside HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same inputs, outputs, flags and results as gpgomea_eval_batch
+ * (the same kernels), but the scratch space is a file-scope device array of
+ * the library of gpgomea_noalloc_scratch_bytes() bytes (64 MiB), held by each
+ * GPU the library runs on until the process ends, and the call allocates
+ * nothing (no hipMalloc or hipFree, no graph instantiation, no events: its
+ * kernels are launched directly on `stream`).  The first call on a device
+ * resolves the array's address there.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller; the array keeps the
+ * last call's contents, and every region a call reads is written by that
+ * call first.  Errors: as gpgomea_eval_batch, and E_WORKSPACE when the shape
+ * needs more scratch than the array holds (about M * (8 KiB + 16 L_max)
+ * bytes). */
+size_t gpgomea_noalloc_scratch_bytes(void);
+int gpgomea_eval_batch_noalloc(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                               int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                               const float* y, uint32_t flags, double* fitness, double* aux,
+                               int8_t* status, void* stream);
 
 /* Fitness and its gradient with respect to every constant.
  *   Same inputs and outputs as gpgomea_eval_batch, plus

@@ -22,7 +22,7 @@ from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  #
 #: repository (load with load_tuning(); the library never reads it by itself)
 TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
-__all__ = ["eval_batch", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
+__all__ = ["eval_batch", "eval_batch_noalloc", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
            "autotune", "load_tuning", "clear_graphs", "graph_count", "flags_of", "profile",
            "profile_report", "op_costs", "GPGOMEAFitness", "LibraryError"]
 
@@ -131,6 +131,28 @@ def eval_batch(ops, consts, X, y, linear_scaling=True, fp64_nodes=False, plain=F
     if return_status:
         out.append(st)
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def eval_batch_noalloc(ops, consts, X, y, fitness, status=None, aux=None, linear_scaling=True,
+                       fp64_nodes=False, plain=False):
+    """gpgomea_eval_batch_noalloc: fitness into the caller's ``fitness``
+    (float64 [M]; ``status`` int8 [M] and ``aux`` float64 [M, 4] optional), with
+    the library's static scratch: the call allocates nothing (the outputs are
+    the caller's)."""
+    torch = _torch()
+    ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
+    fitness = _dev_tensor(fitness, torch.float64, "fitness", dev)
+    if status is not None:
+        status = _dev_tensor(status, torch.int8, "status", dev)
+    if aux is not None:
+        aux = _dev_tensor(aux, torch.float64, "aux", dev)
+    flags = flags_of(linear_scaling, fp64_nodes, plain, graph=False)
+    check(lib.gpgomea_eval_batch_noalloc(
+        ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
+        y.data_ptr(), flags, fitness.data_ptr(), aux.data_ptr() if aux is not None else None,
+        status.data_ptr() if status is not None else None,
+        ctypes.c_void_p(_stream(dev).cuda_stream)))
+    return fitness
 
 
 def grad_consts(ops, consts, X, y, linear_scaling=True, plain=False, graph=True,

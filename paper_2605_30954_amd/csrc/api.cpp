@@ -296,13 +296,14 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof = false;
 std::vector<ProfRec> g_prof_recs;
+thread_local bool t_no_alloc = false;  // the no-allocation entry point is enqueuing
 
 struct ProfScope {
   const char* name;
   hipStream_t s;
   hipEvent_t a = nullptr;
   ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
-    if (g_prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+    if (g_prof && !t_no_alloc && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
   }
   ~ProfScope() {
     if (!a) return;
@@ -556,6 +557,78 @@ extern "C" int gpgomea_eval_batch(const int8_t* ops, int32_t M, int32_t L_max, c
   Call c{s, ops, consts, X, y, fitness, aux, nullptr, status, static_cast<char*>(workspace),
          static_cast<hipStream_t>(stream), false};
   return run_call(c);
+}
+
+// ------------------------------------------------------ no-allocation entry
+// Fitness scratch for callers that cannot allocate: a file-scope device array
+// (each GPU holds its own copy until the process ends).  Host code reaches it
+// only through the address hipGetSymbolAddress gives on each device, taken
+// once per device with that device current; the array's name itself is not a
+// device address on the host.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace gg {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device (resolved on the
+// first call there); E_HIP on failure.
+int scratch_address(void** out) {
+  int dev = 0;
+  GG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GPGOMEA_E_HIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GPGOMEA_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GPGOMEA_OK;
+}
+}  // namespace
+}  // namespace gg
+
+extern "C" size_t gpgomea_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" int gpgomea_eval_batch_noalloc(const int8_t* ops, int32_t M, int32_t L_max,
+                                          const float* consts, int32_t C_max, const float* X,
+                                          int32_t F, int64_t N, int64_t ldx, const float* y,
+                                          uint32_t flags, double* fitness, double* aux,
+                                          int8_t* status, void* stream) {
+  const Shape s{M, L_max, C_max, F, N, ldx, flags};
+  if (!ops || !X || !y || !fitness) return fail(GPGOMEA_E_ARG, "NULL required pointer");
+  if (C_max > 0 && !consts) return fail(GPGOMEA_E_ARG, "consts is NULL but C_max > 0");
+  int rc = check_shape(s);
+  if (rc) return rc;
+  // the fitness path uses the leading regions of the workspace layout only
+  // (statistics, programs, flush events, fit, forward partials, plain ticket)
+  const size_t need = layout_of(s).gpart;
+  if (need > kScratchBytes)
+    return fail(GPGOMEA_E_WORKSPACE,
+                "shape needs %zu bytes of scratch; the no-allocation entry point holds %zu "
+                "(use gpgomea_eval_batch with a workspace)",
+                need, kScratchBytes);
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  (void)hipGetLastError();
+  Call c{s, ops, consts, X, y, fitness, aux, nullptr, status, static_cast<char*>(ws),
+         static_cast<hipStream_t>(stream), false};
+  TileCfg fc;
+  AdjPlan ac;
+  plans_for(s, fc, ac);
+  if (fc.G > 64) return fail(GPGOMEA_E_UNSUPPORTED, "group of more than 64 programs (forward %d)", fc.G);
+  // direct launches only: no graph instantiation, no timing events
+  t_no_alloc = true;
+  rc = enqueue_fused(c, fc, ac);
+  t_no_alloc = false;
+  return rc;
 }
 
 extern "C" int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
