@@ -83,15 +83,29 @@ def _fos_subset(r: int, h: int):
     return np.array([r])
 
 
+def _active(genes_row, gconst_row, slot=0):
+    """The active tree under ``slot`` as a postfix tuple of (symbol, constant
+    bits): what an encoder keeps of the genotype (structure only; a unary
+    operator's operand is its left child)."""
+    g = int(genes_row[slot])
+    if 0 <= g < S.CONST:
+        kids = (2 * slot + 1,) if g in S.UNARY else (2 * slot + 1, 2 * slot + 2)
+        out = ()
+        for k in kids:
+            out += _active(genes_row, gconst_row, k)
+        return out + ((g, 0),)
+    bits = int(np.float32(gconst_row[slot]).view(np.int32)) if g == S.CONST else 0
+    return ((g, bits),)
+
+
 def gom_variants(cfg: Config, genes, gconst, heights, frac: float, salt: int = 0):
     """Replace a fraction of the batch by GOM-style offspring.
 
     An offspring clones a random parent of the same height and copies ONE
     subset of template slots from a random donor of that height (the variation
-    step of Alg. 1), redrawn until at least one copied gene or constant differs
-    from the parent.  Whether the change touches an active slot is not checked
-    here (that would need the encoder); offspring whose change is intronic are
-    still valid individuals.  The batch order is shuffled at the end.
+    step of Alg. 1), redrawn until the copy changes the active tree (Section
+    3.1: only a change to an active part is evaluated), so every offspring is
+    a new program.  The batch order is shuffled at the end.
     """
     rng = rng_for(cfg.cid, STREAM_GOM, salt)
     M = genes.shape[0]
@@ -104,18 +118,18 @@ def gom_variants(cfg: Config, genes, gconst, heights, frac: float, salt: int = 0
     for i in range(n_fresh):
         fresh_by_h.setdefault(int(heights[i]), []).append(i)
     for v in range(n_fresh, M):
-        p = int(rng.integers(0, n_fresh))
-        h = int(heights[p])
-        pool = fresh_by_h[h]
         for _ in range(1000):
+            p = int(rng.integers(0, n_fresh))
+            h = int(heights[p])
+            pool = fresh_by_h[h]
             d = pool[int(rng.integers(0, len(pool)))]
             sub = _fos_subset(int(rng.integers(0, template_size(h))), h)
-            if np.any(genes[d, sub] != genes[p, sub]) or np.any(gconst[d, sub] != gconst[p, sub]):
+            child_g, child_c = genes[p].copy(), gconst[p].copy()
+            child_g[sub] = genes[d, sub]
+            child_c[sub] = gconst[d, sub]
+            if _active(child_g, child_c) != _active(genes[p], gconst[p]):
                 break
-        genes[v] = genes[p]
-        gconst[v] = gconst[p]
-        genes[v, sub] = genes[d, sub]
-        gconst[v, sub] = gconst[d, sub]
+        genes[v], gconst[v] = child_g, child_c
         heights[v] = h
     perm = rng.permutation(M)
     return genes[perm], gconst[perm], heights[perm]

@@ -17,3 +17,5 @@ FUNCS_8 = (ADD, SUB, MUL, DIV, SIN, COS, EXP, LOG)
 FUNCS_ALL = (ADD, SUB, MUL, DIV, SIN, COS, SQ, SQRT, EXP, LOG, POW)
 #: operator set of the formula-ladder experiment (Tab. 2, Experiment III column)
 FUNCS_LADDER = (ADD, SUB, MUL, DIV, SQ, SQRT)
+#: operators with one operand (the others take two)
+UNARY = (SIN, COS, SQ, SQRT, EXP, LOG)
