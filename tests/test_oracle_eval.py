@@ -129,3 +129,36 @@ def test_float32_overflow_emulation():
     assert float(np.float32(np.nextafter(t, 0))) == O.F32_MAX
     with np.errstate(over="ignore"):
         assert np.isinf(np.float32(t))
+
+
+def test_heap_walk_agrees_with_a_scalar_walk_of_the_postfix_program():
+    """tree.py walks the heap-ordered genotype over all rows at once; here
+    each program's postfix form (codec) is parsed and evaluated row by row
+    with scalar Python arithmetic, for operators whose definition needs no
+    protection.  A wrong child slot, operand order or unary operand shows."""
+    from synth import Config, sample_population
+    from synth import symbols as SS
+    F = 4
+    cfg = Config(99, "scalar-walk", 60, (3, 4, 5), (SS.ADD, SS.SUB, SS.MUL, SS.SIN, SS.COS, SS.SQ), F, 16,
+                 "U", -1.5, 1.5, lambda x: x[0])
+    genes, gc, hs = sample_population(cfg, M=60, salt=4)
+    rng = np.random.default_rng(8)
+    X = rng.uniform(-1.5, 1.5, (F, 16))
+    fn = {O.ADD: lambda a, b: a + b, O.SUB: lambda a, b: a - b, O.MUL: lambda a, b: a * b,
+          O.SIN: math.sin, O.COS: math.cos, O.SQ: lambda a: a * a}
+
+    def scalar(node, row):
+        s = node[0]
+        if s == O.CONST:
+            return node[1]
+        if s >= O.VAR0:
+            return float(X[s - O.VAR0, row])
+        return fn[s](*[scalar(k, row) for k in node[2:]])
+
+    for m in range(60):
+        h = int(hs[m])
+        syms, consts = codec.encode_one(genes[m], gc[m], h)
+        tree = codec.parse(np.array(syms, dtype=np.int64), np.array(consts, dtype=np.float32))
+        want = [scalar(tree, r) for r in range(16)]
+        got = TR.evaluate(genes[m], gc[m], h, X)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
