@@ -144,6 +144,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-designs", action="store_true",
+                    help="skip the paper's two evaluation designs (raw-MSE comparators)")
+    ap.add_argument("--design-block", type=int, default=256)
+    ap.add_argument("--design2-blocks", type=int, default=8, help="workgroups per program, design 2")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (writes --tuning) instead of loading the tuning file")
@@ -210,7 +214,8 @@ def roofline(gg, ops, N, stream, step, steps, fit_aux, workload, tuning):
     torch.cuda.synchronize()
     rep = gg.profile_report()
     gg.profile(False)
-    per = {k: v[1] / steps for k, v in rep.items()}          # ms per step
+    counters = {k: v[0] / steps for k, v in rep.items() if k.startswith("fallback_")}
+    per = {k: v[1] / steps for k, v in rep.items() if not k.startswith("fallback_")}  # ms per step
     adj_ms = sum(per.get(k, 0.0) for k in ADJ_PARTS)
     cand = {"fused_forward": per.get("fused_forward", 0.0), "adjoint": adj_ms}
     dom = max(cand, key=cand.get)
@@ -226,6 +231,7 @@ def roofline(gg, ops, N, stream, step, steps, fit_aux, workload, tuning):
             "forward_frac": (alg["fused_forward"] / fwd_s / PEAK_LANE_OPS) if fwd_s else None,
             "forward_alg_lane_ops": alg["fused_forward"],
             "kernels_ms_per_step": per,
+            "binary64_fallback_per_step": counters,
             "op_cost_lane_ops": OP_COST}
 
 
@@ -293,7 +299,7 @@ def cpu_baseline(d, seconds, rows=1_000_000):
                        f"{wall:.1f} s; fitness + forward-mode gradient, float64 NumPy")}
 
 
-def accuracy(d, forms, n_long=3, n_rand=5):
+def accuracy(d, forms, n_long=3, n_rand=5, linear_scaling=True):
     """Error of each timed form against the oracle (its C implementation) on a
     sample of individuals (the longest programs and random ones): error over
     tolerance, where the tolerance is the parity gate plus three times each
@@ -306,7 +312,8 @@ def accuracy(d, forms, n_long=3, n_rand=5):
     idx = sorted(set(np.argsort(-ln, kind="stable")[:n_long].tolist() +
                      rng.choice(len(ln), n_rand, replace=False).tolist()))
     vy = float(np.var(d["y"].astype(np.float64)))
-    sens = fast.sensitivity(d["genes"], d["gc"], d["hs"], d["X"], d["y"], n=2, with_grad=True, indices=idx)
+    sens = fast.sensitivity(d["genes"], d["gc"], d["hs"], d["X"], d["y"], n=2, with_grad=linear_scaling,
+                            linear_scaling=linear_scaling, indices=idx)
     refs = [s["ref"] for s in sens]
     out = {"sample": len(idx)}
     ill = 0
@@ -328,7 +335,7 @@ def accuracy(d, forms, n_long=3, n_rand=5):
                 continue
             tol = 1e-5 * abs(r["fitness"]) + 1e-10 * vy + 3 * s["fit_spread"]
             fe.append(abs(fit[m] - r["fitness"]) / tol)
-            if grad is not None and r["grad"].size:
+            if grad is not None and r.get("grad") is not None and r["grad"].size:
                 g = r["grad"]
                 tol = (1e-5 * np.max(np.abs(g)) + 1e-10 * vy + 4 * 2.0 ** -24 * np.max(r["gabs"]) +
                        3 * s["grad_spread"])
@@ -443,6 +450,34 @@ def main():
         out["speedup_vs_plain"] = ms_plain / ms_step
         forms["plain"] = (fp.cpu().numpy(), gp.cpu().numpy(), sp.cpu().numpy())
 
+    # ---- the paper's two evaluation designs (raw MSE, Eq. 1) next to the
+    # fused path's raw MSE: one pass each over the whole batch
+    raw_forms = {}
+    if not a.no_designs:
+        designs = {"block": a.design_block, "design2_blocks_per_program": a.design2_blocks}
+        runs = (("fused_raw_mse", lambda: gg.eval_batch(ops_d, cs_d, X_d, y_d, linear_scaling=False,
+                                                         return_status=True)),
+                ("design1", lambda: gg.eval_design(ops_d, cs_d, X_d, y_d, design=1, block=a.design_block,
+                                                   return_status=True)),
+                ("design2", lambda: gg.eval_design(ops_d, cs_d, X_d, y_d, design=2, block=a.design_block,
+                                                   blocks_per_program=a.design2_blocks,
+                                                   return_status=True)))
+        with torch.cuda.stream(stream):
+            gg.eval_batch(ops_d, cs_d, X_d, y_d, linear_scaling=False)
+            for dsg in (1, 2):
+                gg.eval_design(ops_d[:8], cs_d[:8], X_d, y_d, design=dsg, block=a.design_block)
+            torch.cuda.synchronize()
+            for name, fn in runs:
+                t0 = time.perf_counter()
+                r = fn()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                designs[name] = {"ms_per_pass": ms, "node_evals_per_s": work / (ms * 1e-3)}
+                raw_forms[name] = (r[0].cpu().numpy(), None, r[1].cpu().numpy())
+        designs["fused_speedup_vs_design1"] = designs["design1"]["ms_per_pass"] / designs["fused_raw_mse"]["ms_per_pass"]
+        designs["fused_speedup_vs_design2"] = designs["design2"]["ms_per_pass"] / designs["fused_raw_mse"]["ms_per_pass"]
+        out["paper_designs_raw_mse"] = designs
+
     # ---- roofline of the dominant kernel (per-kernel hipEvents on the stream)
     if not a.no_roofline:
         _, _, aux_r, st_r = gg.grad_consts(ops_d, cs_d, X_d, y_d, return_aux=True, return_status=True)
@@ -454,6 +489,8 @@ def main():
     if not a.no_accuracy:
         d = {"X": X, "y": y, "genes": genes, "gc": gc, "hs": hs, "lens": lens}
         out["accuracy_vs_oracle"] = accuracy(d, forms)
+        if raw_forms:
+            out["paper_designs_raw_mse"]["accuracy_vs_oracle"] = accuracy(d, raw_forms, linear_scaling=False)
     if a.copy_probe_mb:
         nbytes = a.copy_probe_mb << 20
         src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)

@@ -138,8 +138,9 @@ int gpgomea_eval_batch_noalloc(const int8_t* ops, int32_t M, int32_t L_max, cons
  * dp_r/dc_j.  A protected operator's guarded branch and a clamp outside its
  * range have derivative 0 (a zero partial ends every derivative path through
  * it); sqrt|a| has derivative 0 at a = 0.  Node values are the binary32 ones
- * of the fitness; the chain-rule products dp_r/dc_j are formed in binary32 and
- * the terms summed in binary64.  Where a row span's binary32 sums are not
+ * of the fitness; the chain-rule products dp_r/dc_j are formed in binary32,
+ * each lane sums its rows of one row tile in binary32 (R/64 rows per lane)
+ * and those lane sums are added in binary64.  Where a row span's binary32 sums are not
  * finite (a product formed from the leaves up left the binary32 range) that
  * span is recomputed with binary64 chain-rule products; an entry stays +-inf
  * or NaN only where the binary64 products overflow too.  FP64_NODES is not
@@ -149,6 +150,66 @@ int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, const float
                         const float* y, uint32_t flags, double* fitness, double* aux,
                         double* grad, int8_t* status, void* workspace, size_t workspace_bytes,
                         void* stream);
+
+/* ---- the paper's evaluation designs (comparators) ----------------------------
+ * Section 3.2 ("Evaluation on the GPU") and Fig. 2 describe two ways to lay
+ * the (program, row) sub-evaluations on the GPU; both are kept here so that
+ * the fused batch path can be compared with them at the same accuracy.  Both
+ * compute the raw MSE of Eq. 1 (no linear scaling, as in the paper's designs)
+ * of M programs in the same encoding and layout as gpgomea_eval_batch, with
+ * binary32 nodes and binary64 sums of squared errors.
+ *   gpgomea_eval_design1: one workgroup of `block` threads per program (a
+ *     power of two in [64, 1024]); the program sits in LDS, each thread
+ *     interprets it for rows t, t + block, ... with a private operand stack
+ *     and keeps its squared errors in a register; a tree reduction in LDS
+ *     gives the program's sum.  One launch.
+ *   gpgomea_eval_design2: `blocks_per_program` workgroups per program, each
+ *     over one contiguous block of rows, write partial sums to `partial`
+ *     (device double [M * blocks_per_program], scratch); a second kernel adds
+ *     each program's partials.  Two launches.
+ * fitness (device double [M]) gets the MSE; status (device int8 [M], or NULL)
+ * 0 ok, 1 a prediction was not finite (fitness +inf), 2 bad program (unknown
+ * symbol, variable >= F, more than C_max constants, more than 16 operands on
+ * the stack, not exactly one result; fitness +inf).  Programs are not
+ * compiled or validated beforehand: every check happens while interpreting.
+ * Enqueued on `stream`; nothing is allocated.  Errors: E_SHAPE, E_ARG, E_HIP. */
+int gpgomea_eval_design1(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                         int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                         const float* y, int32_t block, double* fitness, int8_t* status,
+                         void* stream);
+int gpgomea_eval_design2(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                         int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                         const float* y, int32_t block, int32_t blocks_per_program,
+                         double* partial, double* fitness, int8_t* status, void* stream);
+
+/* One Adam step (Kingma & Ba 2015, Alg. 1) on every program's constants, for
+ * constant optimisation driven by gpgomea_grad_consts (the paper names
+ * real-valued constant optimisation as the next thing to integrate with GPU
+ * evaluation, Section 5).  All arrays are device memory, row i belonging to
+ * program i:
+ *   consts        float [M][C_max] in/out: the constants the gradient was taken
+ *                 at; replaced by the step's result (entries whose gradient is
+ *                 0, e.g. unused constants, do not move).
+ *   grad, fitness double [M][C_max] and [M]: gpgomea_grad_consts's outputs at
+ *                 `consts`.
+ *   moments       float [2][M][C_max] in/out: first and second moments; zero
+ *                 before step t = 1.
+ *   best_consts, best_fitness  float [M][C_max], double [M] in/out: the best
+ *                 point seen; before t = 1 set best_fitness to +inf (and
+ *                 best_consts to the start).  A program whose fitness is
+ *                 strictly below best_fitness copies `consts` (the point the
+ *                 fitness belongs to) into best_consts first.
+ *   t             step number, 1, 2, ... (bias corrections 1 - beta^t).
+ * A program whose fitness is not finite returns to best_consts and restarts
+ * its moments.  lr = 0 only records the best point.  The moments and the
+ * step are binary32; 1 - beta and the bias corrections are formed in binary64
+ * from the given values.  Enqueued on `stream`;
+ * nothing is allocated.  Errors: E_SHAPE, E_ARG (NULL arrays, t < 1, lr < 0,
+ * betas outside [0, 1), eps <= 0), E_HIP. */
+int gpgomea_adam_consts(float* consts, int32_t M, int32_t C_max, const double* grad,
+                        const double* fitness, float* moments, float* best_consts,
+                        double* best_fitness, int32_t t, double lr, double beta1, double beta2,
+                        double eps, void* stream);
 
 /* ---- host-side codec (no GPU needed) --------------------------------------
  * Genotype: int8 genes[M][T] heap-ordered over a full binary template (children

@@ -22,7 +22,7 @@ from ._lib import (LINEAR_SCALING, FP64_NODES, PLAIN, NO_GRAPH, LibraryError,  #
 #: repository (load with load_tuning(); the library never reads it by itself)
 TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "mi355x.json")
 
-__all__ = ["eval_batch", "eval_batch_noalloc", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
+__all__ = ["eval_batch", "eval_batch_noalloc", "eval_design", "grad_consts", "encode", "decode", "validate", "workspace_bytes",
            "autotune", "load_tuning", "clear_graphs", "graph_count", "flags_of", "profile",
            "profile_report", "op_costs", "GPGOMEAFitness", "LibraryError"]
 
@@ -153,6 +153,30 @@ def eval_batch_noalloc(ops, consts, X, y, fitness, status=None, aux=None, linear
         status.data_ptr() if status is not None else None,
         ctypes.c_void_p(_stream(dev).cuda_stream)))
     return fitness
+
+
+def eval_design(ops, consts, X, y, design=1, block=256, blocks_per_program=16,
+                return_status=False):
+    """Raw MSE (float64 [M]) with one of the paper's two evaluation designs
+    (gpgomea_eval_design1 / gpgomea_eval_design2): the comparators of the
+    fused path.  ``block`` threads per workgroup; design 2 uses
+    ``blocks_per_program`` workgroups per program."""
+    torch = _torch()
+    ops, consts, X, y, dev, M, L, C, F, N = _prep(ops, consts, X, y)
+    fit = torch.empty(M, dtype=torch.float64, device=dev)
+    st = torch.empty(M, dtype=torch.int8, device=dev)
+    s = ctypes.c_void_p(_stream(dev).cuda_stream)
+    args = (ops.data_ptr(), M, L, consts.data_ptr() if C else None, C, X.data_ptr(), F, N, N,
+            y.data_ptr(), int(block))
+    if design == 1:
+        check(lib.gpgomea_eval_design1(*args, fit.data_ptr(), st.data_ptr(), s))
+    elif design == 2:
+        part = torch.empty(max(1, M * int(blocks_per_program)), dtype=torch.float64, device=dev)
+        check(lib.gpgomea_eval_design2(*args, int(blocks_per_program), part.data_ptr(), fit.data_ptr(),
+                                       st.data_ptr(), s))
+    else:
+        raise ValueError("design must be 1 or 2")
+    return (fit, st) if return_status else fit
 
 
 def grad_consts(ops, consts, X, y, linear_scaling=True, plain=False, graph=True,

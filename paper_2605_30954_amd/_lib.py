@@ -27,6 +27,12 @@ SIGNATURES = {
                                       _p, _p, _p, _p, _sz, _p]),
     "gpgomea_grad_consts": (_c.c_int, [_p, _i32, _i32, _p, _i32, _p, _i32, _i64, _i64, _p, _u32,
                                        _p, _p, _p, _p, _p, _sz, _p]),
+    "gpgomea_eval_design1": (_c.c_int, [_p, _i32, _i32, _p, _i32, _p, _i32, _i64, _i64, _p, _i32,
+                                        _p, _p, _p]),
+    "gpgomea_eval_design2": (_c.c_int, [_p, _i32, _i32, _p, _i32, _p, _i32, _i64, _i64, _p, _i32,
+                                        _i32, _p, _p, _p, _p]),
+    "gpgomea_adam_consts": (_c.c_int, [_p, _i32, _i32, _p, _p, _p, _p, _p, _i32, _c.c_double,
+                                       _c.c_double, _c.c_double, _c.c_double, _p]),
     "gpgomea_noalloc_scratch_bytes": (_sz, []),
     "gpgomea_eval_batch_noalloc": (_c.c_int, [_p, _i32, _i32, _p, _i32, _p, _i32, _i64, _i64, _p, _u32,
                                               _p, _p, _p, _p]),

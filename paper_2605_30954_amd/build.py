@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libgpgomea_eval.so")
 BUILD = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["codec.cpp", "api.cpp", "k_prep.hip", "k_forward.hip", "k_adjoint.hip", "k_opcost.hip"]
+SOURCES = ["codec.cpp", "api.cpp", "k_prep.hip", "k_forward.hip", "k_adjoint.hip", "k_opcost.hip", "k_constopt.hip", "k_designs.hip"]
 
 
 def hipcc():

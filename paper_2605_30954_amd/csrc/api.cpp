@@ -27,6 +27,7 @@ constexpr int kMaxAdjSpans = 256;  // gradient partials per (individual, constan
 constexpr int64_t kAdjPartEntries = int64_t(1) << 26;  // cap on M x C_max x spans (512 MB)
 constexpr int kPlainMaxBlocks = 1024;
 constexpr int kPlainAdjSpans = 1024;  // spans (blocks) of one plain-form adjoint launch
+constexpr size_t kRedoPoolBytes = size_t(4) << 20;  // bad-tile masks (slots of tile_words words)
 constexpr uint32_t kKnownFlags =
     GPGOMEA_LINEAR_SCALING | GPGOMEA_FP64_NODES | GPGOMEA_PLAIN | GPGOMEA_NO_GRAPH;
 
@@ -74,8 +75,8 @@ int plain_adj_spans(int64_t N, int R) {
 
 struct Layout {
   size_t stats, yscr, meta, uops, events, ab, part, plain_part, ticket, gpart, lists, counts, redo,
-      redo_span, plist, pcount, pfb, pfbc, pgpart, pspan, tune, total;
-  int U_stride, ET, lstride, adj_spans;
+      redo_span, rpool, plist, pcount, pfb, pfbc, pgpart, pspan, tune, total;
+  int U_stride, ET, lstride, fbstride, adj_spans;
 };
 
 Layout layout_of(const Shape& s) {
@@ -83,6 +84,7 @@ Layout layout_of(const Shape& s) {
   l.U_stride = s.L_max + 2;
   l.ET = std::max(1, s.L_max);  // flush events per program: at most L_max - 1
   l.lstride = s.M * kAdjChunks;
+  l.fbstride = l.lstride * kAdjParts;  // a binary64 list: up to 4 parts per entry
   l.adj_spans = adj_span_cap(s);
   const size_t M = size_t(s.M), Cm = size_t(std::max(s.C_max, 1));
   size_t o = 0;
@@ -101,16 +103,18 @@ Layout layout_of(const Shape& s) {
   l.plain_part = take(size_t(kPlainMaxBlocks) * 4 * sizeof(double));
   l.ticket = take(64);
   l.gpart = take(M * Cm * l.adj_spans * sizeof(double));
-  l.lists = take(size_t(kAdjClasses + 2) * l.lstride * sizeof(int32_t));  // classes, then 2 fallback
+  // the class lists, then the two binary64 lists (shallow, deep)
+  l.lists = take((size_t(kAdjClasses) * l.lstride + 2 * size_t(l.fbstride)) * sizeof(int32_t));
   l.counts = take(16 * sizeof(int32_t));
   l.redo = take(M * kAdjChunks * sizeof(int32_t));
-  l.redo_span = take(M * kAdjChunks * l.adj_spans);
+  l.redo_span = take(M * kAdjChunks * l.adj_spans * sizeof(int32_t));
+  l.rpool = take(kRedoPoolBytes);  // bad-tile masks of the binary64 fallback
   l.plist = take(M * kAdjChunks * sizeof(int32_t));  // plain form: per-individual entries
   l.pcount = take(M * sizeof(int32_t));
-  l.pfb = take(M * 2 * kAdjChunks * sizeof(int32_t));
+  l.pfb = take(M * 2 * kAdjChunks * kAdjParts * sizeof(int32_t));
   l.pfbc = take(M * 2 * sizeof(int32_t));
   l.pgpart = take(Cm * kPlainAdjSpans * sizeof(double));  // one individual's partials
-  l.pspan = take(size_t(kAdjChunks) * kPlainAdjSpans);
+  l.pspan = take(size_t(kAdjChunks) * kPlainAdjSpans * sizeof(int32_t));
   l.tune = take(M * (Cm + 2) * sizeof(double));  // outputs of the autotuner's trial calls
   l.total = o;
   return l;
@@ -209,7 +213,7 @@ AdjPlan plan_adjoint(const Shape& s, const Tuned* t, int span_cap) {
     a.G = t->G;
     a.Kmask = t->K & 7;
   }
-  const int cap = lds_limit_bytes() - 64;  // static LDS of the kernels
+  const int cap = lds_limit_bytes() - int(kAdjStaticLds);  // static LDS of the path kernels
   a.R = std::max(256, a.R / 256 * 256);
   while (a.R > 256 && adjoint_path_lds_bytes(s.F, a.R, 64, kAdjChunkNC, 4, true) > size_t(cap)) a.R /= 2;
   const int64_t Nr = (s.N + 255) / 256 * 256;
@@ -241,7 +245,7 @@ AdjPlan plan_adjoint(const Shape& s, const Tuned* t, int span_cap) {
 }
 
 bool adjoint_plan_fits(const Shape& s, const AdjPlan& a) {
-  const int cap = lds_limit_bytes() - 64;
+  const int cap = lds_limit_bytes() - int(kAdjStaticLds);
   return adjoint_path_lds_bytes(s.F, a.R, a.G, kAdjChunkNC, 4, false) <= size_t(cap) &&
          adjoint_path_lds_bytes(s.F, a.R, 8, kAdjChunkNC, 4, true) <= size_t(cap);
 }
@@ -296,6 +300,7 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof = false;
 std::vector<ProfRec> g_prof_recs;
+std::map<std::string, long> g_prof_counts;  // work counters of profiled calls
 thread_local bool t_no_alloc = false;  // the no-allocation entry point is enqueuing
 
 struct ProfScope {
@@ -339,6 +344,32 @@ struct Call {
 const char* const kClassName[kAdjClasses] = {"adjoint_c4", "adjoint_c8", "adjoint_c16", "adjoint_c32",
                                              "adjoint_deep"};
 
+// Profiled calls outside graph capture only: how much of the gradient fell
+// back to binary64 (entries, row tiles, spans redone whole).  Synchronises the
+// stream; counted into the profile report.
+void count_fallback(const Call& c, const int* counts, const uint64_t* pool, int tile_words, int pool_cap) {
+  if (!g_prof || t_no_alloc) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c.stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  int32_t h[kAdjClasses + 3] = {};
+  if (hipMemcpyAsync(h, counts, sizeof(h), hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+      hipStreamSynchronize(c.stream) != hipSuccess)
+    return;
+  long tiles = 0;
+  const int slots = std::min(h[kAdjClasses + 2], pool_cap);
+  if (slots > 0 && tile_words > 0) {
+    std::vector<uint64_t> m(size_t(slots) * tile_words);
+    if (hipMemcpyAsync(m.data(), pool, m.size() * 8, hipMemcpyDeviceToHost, c.stream) == hipSuccess &&
+        hipStreamSynchronize(c.stream) == hipSuccess)
+      for (uint64_t w : m) tiles += __builtin_popcountll(w);
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_counts["fallback_entries"] += h[kAdjClasses] + h[kAdjClasses + 1];
+  g_prof_counts["fallback_entry_spans"] += h[kAdjClasses + 2];
+  g_prof_counts["fallback_tiles"] += tiles;
+  g_prof_counts["fallback_pool_overflow"] += std::max(0, h[kAdjClasses + 2] - pool_cap);
+}
+
 // Enqueue the whole pipeline on c.stream.
 int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   const Layout l = layout_of(c.s);
@@ -355,7 +386,11 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   int* lists = reinterpret_cast<int*>(ws + l.lists);
   int* counts = reinterpret_cast<int*>(ws + l.counts);
   int* redo = reinterpret_cast<int*>(ws + l.redo);
-  uint8_t* redo_span = reinterpret_cast<uint8_t*>(ws + l.redo_span);
+  int32_t* redo_span = reinterpret_cast<int32_t*>(ws + l.redo_span);
+  uint64_t* rpool = reinterpret_cast<uint64_t*>(ws + l.rpool);
+  // tile-granular fallback: one mask bit per row tile of a span
+  const int tile_words = ac.tiles_per_span <= 64 * kTileWords ? (ac.tiles_per_span + 63) / 64 : 0;
+  const int pool_cap = tile_words ? int(kRedoPoolBytes / (size_t(tile_words) * 8)) : 0;
   const DataArgs d{c.X, c.s.ldx, c.s.F, c.s.N, c.y};
   const int M = c.s.M;
   const bool grad_work = c.with_grad && c.s.C_max > 0;
@@ -367,11 +402,11 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
 
   // one launch of an adjoint class over `list`
   auto adj = [&](int cls, int K, const int* list, const int* count, int G, int n_groups, int n_spans,
-                 int64_t span_rows, double* gp, int gstride, int gi0, uint8_t* rspan, int rstride, int ebase,
+                 int64_t span_rows, double* gp, int gstride, int gi0, int32_t* rspan, int rstride, int ebase,
                  int* fbl, int* fbc, int fbs, bool split) {
     AdjLaunch L{cls, K, uops, l.U_stride, meta, d, stats, ab, gp, c.s.C_max, gstride, gi0, list, count,
                 ac.R, G, n_groups, n_spans, span_rows, events, l.ET, redo, rspan, rstride, ebase, fbl, fbc,
-                fbs, split};
+                fbs, split, rpool, counts + kAdjClasses + 2, pool_cap, tile_words};
     return launch_adjoint_class(L, c.stream);
   };
 
@@ -391,18 +426,20 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
       int* pfb = reinterpret_cast<int*>(ws + l.pfb);
       int* pfbc = reinterpret_cast<int*>(ws + l.pfbc);
       double* pg = reinterpret_cast<double*>(ws + l.pgpart);
-      uint8_t* pspan = reinterpret_cast<uint8_t*>(ws + l.pspan);
+      int32_t* pspan = reinterpret_cast<int32_t*>(ws + l.pspan);
       GG_TIMED("plain_lists", launch_adjoint_plain_lists(meta, ab, M, plist, pcount, pfbc, redo, c.stream));
       const int P = ac.plain_spans;
       for (int i = 0; i < M; ++i) {
         const int e0 = i * kAdjChunks;
-        int* fb = pfb + 2 * e0;  // this individual's two fallback lists of 8 and their counts
+        // this individual's two binary64 lists (32 parts each) and their counts
+        constexpr int kFb = kAdjChunks * kAdjParts;
+        int* fb = pfb + 2 * kFb * i;
         int* fbc = pfbc + 2 * i;
         GG_TIMED("plain_adjoint", adj(kAdjPlain, 2, plist + e0, pcount + i, kAdjChunks, 1, P, ac.plain_span_rows,
-                                      pg, P, i, pspan, P, e0, fb, fbc, kAdjChunks, true));
+                                      pg, P, i, pspan, P, e0, fb, fbc, kFb, true));
         GG_TIMED("plain_fallback", adj(kAdjFallback, 2, fb, fbc, kAdjChunks, 1, P, ac.plain_span_rows, pg, P, i,
                                        pspan, P, e0, nullptr, nullptr, 0, true));
-        GG_TIMED("plain_fallback", adj(kAdjFallbackWide, 1, fb + kAdjChunks, fbc + 1, kAdjChunks, 1, P,
+        GG_TIMED("plain_fallback", adj(kAdjFallbackWide, 2, fb + kFb, fbc + 1, kAdjChunks, 1, P,
                                        ac.plain_span_rows, pg, P, i, pspan, P, e0, nullptr, nullptr, 0, true));
         GG_TIMED("plain_grad_finalize",
                  launch_grad_finalize(meta, i, 1, c.s.C_max, pg, P, P, stats, ab, c.grad, c.stream));
@@ -416,7 +453,7 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
   GG_TIMED("finalize", launch_finalize(meta, M, part, fc.n_spans, stats, c.s.flags, c.fitness, c.aux,
                                        c.status, ab, c.stream));
   if (grad_work) {
-    int* fbl = lists + size_t(kAdjClasses) * l.lstride;  // two fallback lists, lstride apart
+    int* fbl = lists + size_t(kAdjClasses) * l.lstride;  // two binary64 lists, fbstride apart
     int* fbc = counts + kAdjClasses;
     const int S = ac.n_spans, gs = l.adj_spans;
     GG_TIMED("adjoint_partition",
@@ -425,14 +462,15 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
       if (!ac.on[cls]) continue;
       const int K = cls >= 3 || ((ac.Kmask >> cls) & 1) ? 2 : 4;
       GG_TIMED(kClassName[cls], adj(cls, K, lists + size_t(cls) * l.lstride, counts + cls, ac.G, ac.n_groups[cls],
-                                    S, ac.span_rows, gpart, gs, 0, redo_span, gs, 0, fbl, fbc, l.lstride, false));
+                                    S, ac.span_rows, gpart, gs, 0, redo_span, gs, 0, fbl, fbc, l.fbstride, false));
     }
     GG_TIMED("adjoint_fallback", adj(kAdjFallback, 2, fbl, fbc, ac.fb_G, ac.fb_groups, S, ac.span_rows, gpart, gs,
                                      0, redo_span, gs, 0, nullptr, nullptr, 0, false));
-    GG_TIMED("adjoint_fallback", adj(kAdjFallbackWide, 1, fbl + l.lstride, fbc + 1, ac.fb_G, ac.fb_groups, S,
+    GG_TIMED("adjoint_fallback", adj(kAdjFallbackWide, 2, fbl + l.fbstride, fbc + 1, ac.fb_G, ac.fb_groups, S,
                                      ac.span_rows, gpart, gs, 0, redo_span, gs, 0, nullptr, nullptr, 0, false));
     GG_TIMED("grad_finalize",
              launch_grad_finalize(meta, 0, M, c.s.C_max, gpart, gs, S, stats, ab, c.grad, c.stream));
+    count_fallback(c, counts, rpool, tile_words, pool_cap);
   }
   return GPGOMEA_OK;
 }
@@ -647,6 +685,79 @@ extern "C" int gpgomea_grad_consts(const int8_t* ops, int32_t M, int32_t L_max, 
   return run_call(c);
 }
 
+namespace gg {
+namespace {
+int check_design(const int8_t* ops, int32_t M, int32_t L_max, const float* consts, int32_t C_max,
+                 const float* X, int32_t F, int64_t N, int64_t ldx, const float* y, int32_t block,
+                 double* fitness) {
+  if (M < 0 || L_max < 1 || L_max > GPGOMEA_MAX_LEN || C_max < 0 || C_max > GPGOMEA_MAX_CONSTS ||
+      F < 1 || F > GPGOMEA_MAX_FEATURES || N < 1 || ldx < N)
+    return fail(GPGOMEA_E_SHAPE, "M=%d L_max=%d C_max=%d F=%d N=%lld ldx=%lld outside the limits", M, L_max,
+                C_max, F, (long long)N, (long long)ldx);
+  if (block < 64 || block > 1024 || (block & (block - 1)))
+    return fail(GPGOMEA_E_ARG, "block=%d must be a power of two in [64, 1024]", block);
+  if (M > 0 && (!ops || !X || !y || !fitness || (C_max > 0 && !consts)))
+    return fail(GPGOMEA_E_ARG, "NULL required pointer");
+  return GPGOMEA_OK;
+}
+}  // namespace
+}  // namespace gg
+
+extern "C" int gpgomea_eval_design1(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                                    int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                                    const float* y, int32_t block, double* fitness, int8_t* status,
+                                    void* stream) {
+  using namespace gg;
+  int rc = check_design(ops, M, L_max, consts, C_max, X, F, N, ldx, y, block, fitness);
+  if (rc) return rc;
+  (void)hipGetLastError();
+  const DesignArgs a{ops, M, L_max, consts, C_max, F, X, ldx, N, y, block, fitness, status};
+  GG_HIP(launch_design1(a, static_cast<hipStream_t>(stream)));
+  return GPGOMEA_OK;
+}
+
+extern "C" int gpgomea_eval_design2(const int8_t* ops, int32_t M, int32_t L_max, const float* consts,
+                                    int32_t C_max, const float* X, int32_t F, int64_t N, int64_t ldx,
+                                    const float* y, int32_t block, int32_t blocks_per_program,
+                                    double* partial, double* fitness, int8_t* status, void* stream) {
+  using namespace gg;
+  int rc = check_design(ops, M, L_max, consts, C_max, X, F, N, ldx, y, block, fitness);
+  if (rc) return rc;
+  if (blocks_per_program < 1 || int64_t(blocks_per_program) * M > (int64_t(1) << 31) - 1)
+    return fail(GPGOMEA_E_ARG, "blocks_per_program=%d (M=%d) out of range", blocks_per_program, M);
+  if (M > 0 && !partial) return fail(GPGOMEA_E_ARG, "NULL partial");
+  (void)hipGetLastError();
+  const DesignArgs a{ops, M, L_max, consts, C_max, F, X, ldx, N, y, block, fitness, status};
+  GG_HIP(launch_design2(a, blocks_per_program, partial, static_cast<hipStream_t>(stream)));
+  return GPGOMEA_OK;
+}
+
+extern "C" int gpgomea_adam_consts(float* consts, int32_t M, int32_t C_max, const double* grad,
+                                   const double* fitness, float* moments, float* best_consts,
+                                   double* best_fitness, int32_t t, double lr, double beta1,
+                                   double beta2, double eps, void* stream) {
+  using namespace gg;
+  if (M < 0 || C_max < 0 || C_max > GPGOMEA_MAX_CONSTS)
+    return fail(GPGOMEA_E_SHAPE, "M=%d, C_max=%d outside [0, %d]", M, C_max, GPGOMEA_MAX_CONSTS);
+  if (t < 1) return fail(GPGOMEA_E_ARG, "step number t=%d must be >= 1", t);
+  if (!(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return fail(GPGOMEA_E_ARG, "need lr >= 0, 0 <= beta1, beta2 < 1, eps > 0");
+  if (M == 0) return GPGOMEA_OK;
+  if (!fitness || !best_fitness) return fail(GPGOMEA_E_ARG, "NULL fitness or best_fitness");
+  if (C_max > 0 && (!consts || !grad || !moments || !best_consts))
+    return fail(GPGOMEA_E_ARG, "NULL consts, grad, moments or best_consts with C_max > 0");
+  // 1 - beta and the bias corrections in binary64 (in binary32 they cancel:
+  // 1 - float(0.999) is 1.3e-5 away from 0.001, relatively)
+  const AdamParams p{float(lr), float(beta1), float(beta2), float(eps), float(1.0 - beta1),
+                     float(1.0 - beta2), float(1.0 - std::pow(beta1, t)), float(1.0 - std::pow(beta2, t))};
+  if (!(p.bias1 > 0.0f) || !(p.bias2 > 0.0f)) return fail(GPGOMEA_E_ARG, "bias correction is zero");
+  const size_t mc = size_t(M) * size_t(C_max);
+  (void)hipGetLastError();
+  GG_HIP(launch_adam_consts(consts, M, C_max, grad, fitness, moments, moments + mc, best_consts,
+                            best_fitness, p, static_cast<hipStream_t>(stream)));
+  return GPGOMEA_OK;
+}
+
 extern "C" int gpgomea_clear_graphs(void) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   for (auto& kv : g_graphs) destroy_entry(kv.second);
@@ -689,6 +800,11 @@ extern "C" int gpgomea_profile_report(char* buf, int32_t len) {
       (void)hipEventDestroy(r.b);
     }
     pending.clear();
+    {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      for (auto& kv : g_prof_counts) acc[kv.first] = {kv.second, 0.0};
+      g_prof_counts.clear();
+    }
     for (auto& kv : acc) {
       char line[160];
       std::snprintf(line, sizeof(line), "%s %ld %.6f\n", kv.first.c_str(), kv.second.first,

@@ -69,17 +69,39 @@ struct AdjParams {
   const uint2* events; // flush events [M][ET]
   int ET;
   int* redo;           // [M * 8] per entry: some span fell back (cleared by the partition)
-  uint8_t* redo_span;  // [(e - ebase) * rstride + span]: that span's sums were not finite
+  int32_t* redo_span;  // [(e - ebase) * rstride + span]: 0 the span's binary32 sums are whole,
+                       // -1 every tile of it is redone in binary64, k > 0 the tiles set in
+                       // pool slot k - 1 are
   int rstride, ebase;
-  int* fb_list;        // fallen-back entries, appended by the binary32 kernels: at most 8
-  int* fb_count;       // constants and 4 stack slots at fb_list[0 ..] (count fb_count[0]),
-  int fb_stride;       // the others at fb_list[fb_stride ..] (count fb_count[1])
+  int* fb_list;        // parts (entry * 4 + q: constants 8q .. 8q + 7 of the entry's chunk)
+  int* fb_count;       // of the fallen-back entries, appended by the binary32 kernels: at most
+  int fb_stride;       // 4 stack slots at fb_list[0 ..] (count fb_count[0]), the others at
+                       // fb_list[fb_stride ..] (count fb_count[1])
+  uint64_t* pool;      // bad-tile masks, tile_words words per slot
+  int* pool_count;     // slots taken (cleared by the partition)
+  int pool_cap;
+  int tile_words;      // words per mask; 0: spans are redone whole (plain form, long spans)
 };
 
 constexpr int kChunk = 32;       // constants per entry of the chunked classes
 constexpr int kMaxChunks = 8;    // GPGOMEA_MAX_CONSTS / kChunk
 constexpr int kShallow = 4;      // stack slots of the shallow classes
 constexpr int kPathWaves = 4;
+constexpr int kAdjItems = 2048;  // work items a short class list is spread over
+constexpr int kSub = 8;          // constants per item of the binary64 lists
+constexpr int kSubs = kChunk / kSub;
+
+// A list item: the class lists hold entries (individual * 8 + chunk of 32);
+// the binary64 lists hold entry * 4 + part, each part 8 constants of its
+// entry's chunk.  e: the entry, c_lo: the item's first constant ordinal.
+struct Item {
+  int e, c_lo;
+};
+template <bool SUB>
+__device__ inline Item item_of(int v) {
+  if constexpr (SUB) return {v / kSubs, ((v / kSubs) & (kMaxChunks - 1)) * kChunk + (v % kSubs) * kSub};
+  return {v, (v & (kMaxChunks - 1)) * kChunk};
+}
 
 template <typename C, int K>
 using CVec = typename VecT<C, K>::type;
@@ -154,6 +176,7 @@ __global__ __launch_bounds__(kPartThreads) void k_adj_partition(
     for (int q = 0; q < kAdjClasses; ++q) counts[q] = sc[q][t];
     counts[kAdjClasses] = 0;  // fallback lists
     counts[kAdjClasses + 1] = 0;
+    counts[kAdjClasses + 2] = 0;  // bad-tile mask pool
   }
 }
 
@@ -329,19 +352,33 @@ struct TArr {
 };
 
 // T[e] *= f for e in [lo, hi) (local entries; lo may be negative, hi may
-// exceed NC), expanded over the compile-time entry index: two uniform compares
-// per entry up to the range's end.
-template <int E, int K, int NC, typename C>
+// exceed NC).  A switch on the first entry (a binary search of uniform
+// compares) enters one unrolled chain over the compile-time entry index, which
+// then costs one uniform compare per entry up to the range's end.
+#define GG_SCALE_CASE(E)                       \
+  case E:                                      \
+    if constexpr (E < NC) {                    \
+      if (E >= hi) break;                      \
+      T.v[E] = zmul<K, C>(f, T.v[E]);          \
+    }                                          \
+    [[fallthrough]];
+template <int K, int NC, typename C>
 __device__ inline void scale_range(TArr<K, NC, C>& T, int lo, int hi, const CVec<C, K>& f) {
-  if constexpr (E < NC) {
-    if (E >= hi) return;
-    if (E >= lo) {
-      T.v[E] = zmul<K, C>(f, T.v[E]);
-      GG_BRANCH();
-    }
-    scale_range<E + 1, K, NC, C>(T, lo, hi, f);
+  static_assert(NC <= 32, "the chain below has 32 entries");
+  switch (lo < 0 ? 0 : lo) {
+    GG_SCALE_CASE(0) GG_SCALE_CASE(1) GG_SCALE_CASE(2) GG_SCALE_CASE(3)
+    GG_SCALE_CASE(4) GG_SCALE_CASE(5) GG_SCALE_CASE(6) GG_SCALE_CASE(7)
+    GG_SCALE_CASE(8) GG_SCALE_CASE(9) GG_SCALE_CASE(10) GG_SCALE_CASE(11)
+    GG_SCALE_CASE(12) GG_SCALE_CASE(13) GG_SCALE_CASE(14) GG_SCALE_CASE(15)
+    GG_SCALE_CASE(16) GG_SCALE_CASE(17) GG_SCALE_CASE(18) GG_SCALE_CASE(19)
+    GG_SCALE_CASE(20) GG_SCALE_CASE(21) GG_SCALE_CASE(22) GG_SCALE_CASE(23)
+    GG_SCALE_CASE(24) GG_SCALE_CASE(25) GG_SCALE_CASE(26) GG_SCALE_CASE(27)
+    GG_SCALE_CASE(28) GG_SCALE_CASE(29) GG_SCALE_CASE(30) GG_SCALE_CASE(31)
+    default:
+      break;
   }
 }
+#undef GG_SCALE_CASE
 // T[lo] = f (no entry when lo lies outside [0, NC)).
 template <int E, int K, int NC, typename C>
 __device__ inline void assign_at(TArr<K, NC, C>& T, int lo, const CVec<C, K>& f) {
@@ -363,7 +400,7 @@ __device__ inline void path_flush(TArr<K, NC, C>& T, uint32_t side, int c_lo, co
     assign_at<0, K, NC, C>(T, lo, f);
     GG_BRANCH();
   } else {
-    scale_range<0, K, NC, C>(T, lo, lo + n, f);
+    scale_range<K, NC, C>(T, lo, lo + n, f);
     GG_BRANCH();
   }
 }
@@ -577,6 +614,8 @@ template <int K, int D, int W, int NC, bool ROLL, typename C, bool SPLIT>
 __global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr bool F64 = sizeof(C) == 8;
+  constexpr bool SUB = F64;  // the binary64 pass works on parts of 8 constants
+  static_assert(!SUB || NC == kSub, "binary64 items hold 8 constants");
   constexpr int COPIES = SPLIT ? W : 1;
   const int R = p.R;
   float* xs = reinterpret_cast<float*>(smem_raw);
@@ -585,7 +624,11 @@ __global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
 
   const AdjItem it = adj_item(p);
   const int cnt = __builtin_amdgcn_readfirstlane(*p.count);
-  if (it.slot * p.G >= cnt) return;  // whole block: nothing of this list here
+  // group size: G, or smaller for a short list so that its (span, group) work
+  // items still number about kAdjItems; at least two entries per wave, so the
+  // waves' shares of a group stay balanced
+  const int G = max(min(2 * W, p.G), min(p.G, int(int64_t(cnt) * p.n_spans / kAdjItems)));
+  if (it.slot * G >= cnt) return;  // whole block: nothing of this list here
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const double ybar = p.stats[ST_YBAR];
@@ -599,21 +642,44 @@ __global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
   const uint2 endu = make_uint2(UOP_END_HDR, 0u), zero2 = make_uint2(0u, 0u);
 
   __shared__ int queue;
-  for (int grp = it.slot; grp * p.G < cnt; grp += p.n_groups) {  // block-uniform
-    const int base = grp * p.G;
-    const int Gn = min(p.G, cnt - base);
+  // one bit per row tile of the span and group entry: binary32 pass, the
+  // tiles whose sums were not finite (left out of the partials); binary64
+  // pass, the tiles to redo.  rstate: the entries' redo states.
+  __shared__ uint64_t tmask[64][kTileWords];
+  __shared__ int rstate[64];
+  const bool tiled = !SPLIT && p.tile_words > 0;
+  for (int grp = it.slot; grp * G < cnt; grp += p.n_groups) {  // block-uniform
+    const int base = grp * G;
+    const int Gn = min(G, cnt - base);
     // lane j holds the group's j-th entry (G <= 64)
     const int lst = lane < Gn ? p.list[base + lane] : 0;
     if constexpr (F64) {  // nothing flagged on this span: skip it, staging included
       bool any = false;
-      for (int jj = 0; jj < Gn; ++jj) any = any || span_flagged(p, p.list[base + jj], it.span);
+      for (int jj = 0; jj < Gn; ++jj) any = any || span_flagged(p, item_of<SUB>(p.list[base + jj]).e, it.span);
       if (!any) continue;
     }
     __syncthreads();  // previous group's partials written
     for (int j = threadIdx.x; j < COPIES * GC; j += blockDim.x) gacc[j] = 0.0;
+    if (tiled) {
+      for (int j = threadIdx.x; j < 64 * kTileWords; j += blockDim.x) {
+        const int jj = j / kTileWords, w = j - jj * kTileWords;
+        uint64_t m = 0;
+        if (F64 && jj < Gn && w < p.tile_words) {
+          const int st = p.redo_span[size_t(item_of<SUB>(p.list[base + jj]).e - p.ebase) * p.rstride + it.span];
+          m = st < 0 ? ~uint64_t(0) : st > 0 ? p.pool[size_t(st - 1) * p.tile_words + w] : 0;
+        }
+        tmask[jj][w] = m;
+      }
+    }
     for (int64_t r0 = s_begin; r0 < s_end; r0 += R) {
       const int nvalid = int(min<int64_t>(R, s_end - r0));
+      const int tile = int((r0 - s_begin) / R);
       __syncthreads();
+      if (F64 && tiled) {  // no entry of the group redoes this tile: skip it (block-uniform)
+        bool need = false;
+        for (int jj = 0; jj < Gn; ++jj) need = need || ((tmask[jj][tile >> 6] >> (tile & 63)) & 1);
+        if (!need) continue;
+      }
       if (threadIdx.x == 0) queue = 0;
       stage_x_async<W>(xs, p.X, p.ldx, p.F, R, r0, p.N);
       stage_y(yts, p.y, R, r0, nvalid, ybar);
@@ -626,29 +692,31 @@ __global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
       LaneWords iw, iw_next;  // n_const, then s0, s1 and the inverse scale as six words
       int jj = SPLIT ? 0 : claim_next(&queue);
       if (jj < Gn) {
-        const int i0 = __builtin_amdgcn_readlane(lst, jj) >> 3;
+        const int i0 = item_of<SUB>(__builtin_amdgcn_readlane(lst, jj)).e >> 3;
         load_window(p.uops + size_t(i0) * p.U_stride, 0, p.U_stride, endu, u0lo, u0hi);
         load_window(p.events + size_t(i0) * p.ET, 0, p.ET, zero2, e0lo, e0hi);
         iw.load(meta_w + size_t(i0) * kMetaWords + kMetaNConst, 1, ab_w + size_t(i0) * 2 * AB_WORDS, 6);
       }
       while (jj < Gn) {  // wave-uniform
-        const int e = __builtin_amdgcn_readlane(lst, jj);
+        const Item itm = item_of<SUB>(__builtin_amdgcn_readlane(lst, jj));
+        const int e = itm.e;
         const int i = e >> 3;
-        const int c_lo = (e & (kMaxChunks - 1)) * kChunk;
+        const int c_lo = itm.c_lo;
         const int nc = int(iw.get(0));
         const double s0m = words_double(iw.get(1), iw.get(2)) - ybar;
         const double s1 = words_double(iw.get(3), iw.get(4));
         const double isc = words_double(iw.get(5), iw.get(6));
         const int jn = SPLIT ? jj + 1 : claim_next(&queue);
         if (jn < Gn) {
-          const int i1 = __builtin_amdgcn_readlane(lst, jn) >> 3;
+          const int i1 = item_of<SUB>(__builtin_amdgcn_readlane(lst, jn)).e >> 3;
           load_window(p.uops + size_t(i1) * p.U_stride, 0, p.U_stride, endu, u1lo, u1hi);
           load_window(p.events + size_t(i1) * p.ET, 0, p.ET, zero2, e1lo, e1hi);
           iw_next.load(meta_w + size_t(i1) * kMetaWords + kMetaNConst, 1, ab_w + size_t(i1) * 2 * AB_WORDS, 6);
         }
         const int ncl = min(NC, nc - c_lo);  // constants this entry tracks
         bool run = true;
-        if constexpr (F64) run = span_flagged(p, e, it.span);
+        if constexpr (F64)
+          run = tiled ? ((tmask[jj][tile >> 6] >> (tile & 63)) & 1) != 0 : span_flagged(p, e, it.span);
         if (run) {
           C cols[NC];
 #pragma unroll
@@ -673,7 +741,20 @@ __global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
               sink_cols<0, K, NC, C, false>(cols, T, g, ncl, kv);
             }
           }
-          flush_cols<0, NC, C>(cols, ncl, gmine + size_t(jj) * NC);
+          if (!F64 && tiled) {
+            // a column sum that is not finite: this tile of the entry is left
+            // out and redone in binary64 (wave-uniform decision)
+            bool lbad = false;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) lbad = lbad || (k < ncl && !isfinite(cols[k]));
+            if (__ballot(lbad) != 0) {
+              if (lane == 0) tmask[jj][tile >> 6] |= uint64_t(1) << (tile & 63);
+            } else {
+              flush_cols<0, NC, C>(cols, ncl, gmine + size_t(jj) * NC);
+            }
+          } else {
+            flush_cols<0, NC, C>(cols, ncl, gmine + size_t(jj) * NC);
+          }
         }
         u0lo = u1lo;
         u0hi = u1hi;
@@ -690,31 +771,59 @@ __global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
         for (int w = 1; w < W; ++w) gacc[j] += gacc[size_t(w) * GC + j];
       }
     }
-    // each thread writes what it summed
-    for (int j = threadIdx.x; j < GC; j += blockDim.x) {
-      const int jj = j / NC, k = j - jj * NC;
-      if (jj >= Gn) continue;
-      const int e = p.list[base + jj];
-      const int i = e >> 3, cj = (e & (kMaxChunks - 1)) * kChunk + k;
-      if (cj >= p.meta[i].n_const) continue;
-      if (F64 && !span_flagged(p, e, it.span)) continue;
-      p.gpart[(size_t(i - p.gi0) * p.C_max + cj) * p.gstride + it.span] = gacc[j];
-    }
     if constexpr (!F64) {
-      // sums that are not finite: that span of the entry is redone in binary64.
-      // The first span of an entry to fall back appends it to the fallback list
-      // (whose order does not change any result)
+      // the entries' redo states on this span: tiled, the tiles left out (their
+      // mask goes to a pool slot; a full pool redoes the whole span); untiled,
+      // sums that are not finite redo the whole span.  The first span of an
+      // entry to fall back appends it to the fallback list (whose order does
+      // not change any result)
       for (int jj = threadIdx.x; jj < Gn; jj += blockDim.x) {
         const int e = p.list[base + jj];
         const int ncl = min(NC, p.meta[e >> 3].n_const - (e & (kMaxChunks - 1)) * kChunk);
-        bool bad = false;
-        for (int k = 0; k < ncl; ++k) bad = bad || !isfinite(gacc[size_t(jj) * NC + k]);
-        p.redo_span[size_t(e - p.ebase) * p.rstride + it.span] = bad ? 1 : 0;
-        if (bad && atomicExch(&p.redo[e], 1) == 0) {
-          const int wide = (ncl > 8 || p.meta[e >> 3].slots > kShallow) ? 1 : 0;
-          const int slot = atomicAdd(p.fb_count + wide, 1);
-          p.fb_list[size_t(wide) * p.fb_stride + slot] = e;
+        int st = 0;
+        if (tiled) {
+          bool any = false;
+          for (int w = 0; w < p.tile_words; ++w) any = any || tmask[jj][w] != 0;
+          if (any) {
+            const int slot = atomicAdd(p.pool_count, 1);
+            if (slot < p.pool_cap) {
+              for (int w = 0; w < p.tile_words; ++w) p.pool[size_t(slot) * p.tile_words + w] = tmask[jj][w];
+              st = slot + 1;
+            } else {
+              st = -1;
+            }
+          }
+        } else {
+          bool bad = false;
+          for (int k = 0; k < ncl; ++k) bad = bad || !isfinite(gacc[size_t(jj) * NC + k]);
+          st = bad ? -1 : 0;
         }
+        rstate[jj] = st;
+        p.redo_span[size_t(e - p.ebase) * p.rstride + it.span] = st;
+        if (st != 0 && atomicExch(&p.redo[e], 1) == 0) {
+          // its parts of 8 constants go to the binary64 list of its depth
+          const int deep = p.meta[e >> 3].slots > kShallow ? 1 : 0;
+          const int parts = (ncl + kSub - 1) / kSub;
+          const int slot = atomicAdd(p.fb_count + deep, parts);
+          for (int q = 0; q < parts; ++q) p.fb_list[size_t(deep) * p.fb_stride + slot + q] = e * kSubs + q;
+        }
+      }
+      __syncthreads();
+    }
+    // each thread writes what it summed.  Binary32: the sums of the tiles kept
+    // (0 where the whole span is redone); binary64: adds the redone tiles
+    for (int j = threadIdx.x; j < GC; j += blockDim.x) {
+      const int jj = j / NC, k = j - jj * NC;
+      if (jj >= Gn) continue;
+      const Item itm = item_of<SUB>(p.list[base + jj]);
+      const int e = itm.e;
+      const int i = e >> 3, cj = itm.c_lo + k;
+      if (cj >= p.meta[i].n_const) continue;
+      double* dst = p.gpart + (size_t(i - p.gi0) * p.C_max + cj) * p.gstride + it.span;
+      if constexpr (F64) {
+        if (span_flagged(p, e, it.span)) *dst += gacc[j];
+      } else {
+        *dst = rstate[jj] < 0 ? 0.0 : gacc[j];
       }
     }
   }
@@ -769,20 +878,21 @@ hipError_t launch_adjoint_class(const AdjLaunch& L, hipStream_t s) {
   const AdjParams ap{L.uops, L.U_stride, L.meta, L.d.X, L.d.ldx, L.d.F, L.d.N, L.d.y, L.stats, L.ab,
                      L.gpart, L.C_max, L.gstride, L.gi0, L.list, L.count, L.R, L.G, L.n_groups,
                      L.n_spans, L.span_rows, L.events, L.ET, L.redo, L.redo_span, L.rstride,
-                     L.ebase, L.fb_list, L.fb_count, L.fb_stride};
+                     L.ebase, L.fb_list, L.fb_count, L.fb_stride, L.pool, L.pool_count, L.pool_cap,
+                     L.split ? 0 : L.tile_words};
   if (L.G < 1 || L.G > 64) return hipErrorInvalidValue;  // the group list is lane-held
   const bool roll = L.U_stride > 64;
-  if (L.cls == kAdjFallback) {  // binary64 chain rule: at most 8 constants, 4 slots
-    if (L.split) return roll ? path_launch<2, kShallow, 8, true, double, true>(ap, s)
-                             : path_launch<2, kShallow, 8, false, double, true>(ap, s);
-    return roll ? path_launch<2, kShallow, 8, true, double, false>(ap, s)
-                : path_launch<2, kShallow, 8, false, double, false>(ap, s);
+  if (L.cls == kAdjFallback) {  // binary64 chain rule: parts of 8 constants, 4 slots
+    if (L.split) return roll ? path_launch<2, kShallow, kSub, true, double, true>(ap, s)
+                             : path_launch<2, kShallow, kSub, false, double, true>(ap, s);
+    return roll ? path_launch<2, kShallow, kSub, true, double, false>(ap, s)
+                : path_launch<2, kShallow, kSub, false, double, false>(ap, s);
   }
-  if (L.cls == kAdjFallbackWide) {  // binary64 chain rule, any entry (32 constants, 8 slots)
-    if (L.split) return roll ? path_launch<1, 8, kChunk, true, double, true>(ap, s)
-                             : path_launch<1, 8, kChunk, false, double, true>(ap, s);
-    return roll ? path_launch<1, 8, kChunk, true, double, false>(ap, s)
-                : path_launch<1, 8, kChunk, false, double, false>(ap, s);
+  if (L.cls == kAdjFallbackWide) {  // binary64 chain rule: parts of 8 constants, 8 slots
+    if (L.split) return roll ? path_launch<2, 8, kSub, true, double, true>(ap, s)
+                             : path_launch<2, 8, kSub, false, double, true>(ap, s);
+    return roll ? path_launch<2, 8, kSub, true, double, false>(ap, s)
+                : path_launch<2, 8, kSub, false, double, false>(ap, s);
   }
   if (L.cls == kAdjPlain) {  // plain form: any shallow or deep entry, waves share it
     return roll ? path_launch<2, 8, kChunk, true, float, true>(ap, s)

@@ -90,6 +90,7 @@ constexpr int kAdjFallbackWide = 6;
 constexpr int kAdjPlain = 7;
 constexpr int kAdjChunks = 8;   // entries per individual at most (GPGOMEA_MAX_CONSTS / 32)
 constexpr int kAdjChunkNC = 32;  // constants per entry of the chunked classes
+constexpr int kAdjParts = 4;  // binary64 list items per entry (8 constants each)
 
 // One class launch: the entries list[0 .. *count) over n_spans spans of
 // span_rows rows, G entries per group, n_groups group slots per span (blocks
@@ -111,13 +112,21 @@ struct AdjLaunch {
   const uint2* events;
   int ET;
   int* redo;
-  uint8_t* redo_span;
+  int32_t* redo_span;
   int rstride, ebase;
   int* fb_list;
   int* fb_count;
   int fb_stride;
   bool split;
+  uint64_t* pool;  // bad-tile masks (tile_words words per slot), pool_cap slots
+  int* pool_count;
+  int pool_cap, tile_words;
 };
+// Tile-granular binary64 fallback: one bit per row tile of a span, at most
+// 64 * kTileWords tiles per span (else the fallback redoes whole spans).
+constexpr int kTileWords = 4;
+// static LDS of the path kernels (tile masks and redo states of a group)
+constexpr size_t kAdjStaticLds = 64 * kTileWords * 8 + 64 * 4 + 16;
 
 // lists[c * lstride + k] (c < kAdjClasses), counts[c]; counts[kAdjClasses],
 // counts[kAdjClasses + 1] = 0 (the fallback lists); redo[i * 8 + k] = 0
@@ -131,6 +140,33 @@ hipError_t launch_adjoint_class(const AdjLaunch& L, hipStream_t s);
 hipError_t launch_grad_finalize(const ProgMeta* meta, int i0, int M, int C_max, const double* gpart,
                                 int gstride, int n_spans, const double* stats, const double* ab,
                                 double* grad, hipStream_t s);
+// The paper's two evaluation designs (comparators of the fused path): raw MSE
+// of M programs, one workgroup (design 1) or nb workgroups plus an
+// aggregation kernel (design 2) per program; part = M * nb doubles.
+struct DesignArgs {
+  const int8_t* ops;
+  int M, L;
+  const float* consts;
+  int C, F;
+  const float* X;
+  int64_t ldx, N;
+  const float* y;
+  int block;
+  double* fitness;
+  int8_t* status;
+};
+hipError_t launch_design1(const DesignArgs& a, hipStream_t s);
+hipError_t launch_design2(const DesignArgs& a, int nb, double* part, hipStream_t s);
+// One Adam step on every program's constants (constants [M, C] in place,
+// moments mom1/mom2 [M, C], best constants / fitness kept per program).
+struct AdamParams {
+  float lr, beta1, beta2, eps;
+  float omb1, omb2;    // 1 - beta1, 1 - beta2 (formed in binary64 from the caller's values)
+  float bias1, bias2;  // 1 - beta1^t, 1 - beta2^t (likewise)
+};
+hipError_t launch_adam_consts(float* consts, int M, int C, const double* grad, const double* fitness,
+                              float* mom1, float* mom2, float* best_c, double* best_f,
+                              const AdamParams& p, hipStream_t s);
 // LDS bytes of one path-class block (row tile, centred targets, constant
 // accumulators: one copy, or W with split)
 size_t adjoint_path_lds_bytes(int F, int R, int G, int NC, int W, bool split);

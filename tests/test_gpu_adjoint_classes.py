@@ -246,3 +246,34 @@ def test_graph_cache_changing_batch_size():
             gg.eval_batch(ops[:8], cs[:8], X[:, :n].contiguous(), y[:n].contiguous())
     s.synchronize()
     assert 1 <= gg.graph_count() <= 16, gg.graph_count()
+
+
+def test_binary64_redo_of_single_row_tiles():
+    """x0 / (c - x1) with c just above x1 at three rows, where x0 = 1e28: the
+    value stays in the binary32 range but d/dc = -x0 / (c - x1)^2 does not,
+    so the binary32 sums of the row tiles holding those rows are left out and
+    redone in binary64 (two of the rows share a span, in different tiles; the
+    third is in another span).  400,000 rows give several tiles per span.  The
+    overflowing rows dominate the gradient of the raw MSE (their residuals are
+    6% of their values), so a tile lost or counted twice shows; with linear
+    scaling the fit would absorb those rows and leave a cancelling sum.  One,
+    10 and 20 constants (three work classes), fused and plain."""
+    rng = np.random.default_rng(17)
+    F, N = 3, 400_000
+    X = rng.uniform(-1, 1, (F, N)).astype(np.float32)
+    rows = [123_457, 124_057, 300_001]
+    X[0, rows] = [1e28, 2e28, 3e28]
+    X[1, rows] = np.float32(1.999998)
+    x = X.astype(np.float64)
+    y = (x[0] / (2.0 - x[1]) + 0.1 * x[2]).astype(np.float32)
+    assert np.all(np.isfinite(y))
+    trigger = [V[0], C, V[1], O.SUB, O.DIV]
+    progs = [balanced([trigger] + [[C, V[2], O.MUL]] * n) for n in (0, 9, 19)]
+    progs.append([C, V[2], O.MUL, C, O.ADD])                      # no overflow anywhere
+    ops, cs = pack(progs, 511, 32, rng)
+    cs[:3, 0] = np.float32(1.9999999)
+    log(f"[case] tile-granular binary64 redo: N={N}, rows {rows}")
+    f, g, st = check_against_oracle(ops, cs, X, y, 8, "single-row tile redo", ls=False)
+    assert np.all(st == 0)
+    assert np.all(np.isfinite(g)) and np.all(np.abs(g[:3, 0]) > 1e60)
+    check_against_oracle(ops, cs, X, y, 8, "single-row tile redo, plain", ls=False, plain=True)
