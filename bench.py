@@ -146,6 +146,8 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-designs", action="store_true",
                     help="skip the paper's two evaluation designs (raw-MSE comparators)")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the context lines of the height-4 and height-5 workloads")
     ap.add_argument("--design-block", type=int, default=256)
     ap.add_argument("--design2-blocks", type=int, default=8, help="workgroups per program, design 2")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -348,6 +350,32 @@ def accuracy(d, forms, n_long=3, n_rand=5, linear_scaling=True):
     return out
 
 
+def other_workload(gg, cid, steps, stream):
+    """Fused fitness + gradient on another workload (full size, shipped
+    tuning, graph replays): ms per step and node-evals/s, as context."""
+    import numpy as np
+    import torch
+    from synth import get_config, make_dataset, sample_population
+    cfg = get_config(cid)
+    X, y = make_dataset(cfg)
+    genes, gc, hs = sample_population(cfg)
+    hv = hs if len(set(hs.tolist())) > 1 else int(hs[0])
+    ops, cs, lens, _ = gg.encode(genes, gc, hv, cfg.L_max, cfg.C_max)
+    dev = torch.device("cuda:0")
+    t = lambda arr: torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+    o, c, Xd, yd = t(ops), t(cs), t(X), t(y)
+    work = int(lens.astype(np.int64).sum()) * cfg.N
+    with torch.cuda.stream(stream):
+        gg.grad_consts(o, c, Xd, yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gg.grad_consts(o, c, Xd, yd)
+        torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": f"cfg{cid}: {cfg.description}", "ms_per_step": ms, "node_evals_per_s": work / (ms * 1e-3)}
+
+
 def main():
     a = parse()
     if a.pmc_summary:
@@ -484,6 +512,8 @@ def main():
         fit_aux = (st_r.cpu().numpy(), aux_r[:, 1].cpu().numpy(), nconst)
         out["roofline"] = roofline(gg, ops, N, stream, step, max(1, min(a.steps, 3)), fit_aux,
                                    a.workload, tuning)
+    if not a.no_other_workloads and a.workload == 5:
+        out["other_workloads"] = {f"cfg{cid}": other_workload(gg, cid, 10, stream) for cid in (2, 4)}
     if base is not None:
         out["cpu_baseline"] = base
     if not a.no_accuracy:

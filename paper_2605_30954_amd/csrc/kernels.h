@@ -124,7 +124,7 @@ struct AdjLaunch {
 };
 // Tile-granular binary64 fallback: one bit per row tile of a span, at most
 // 64 * kTileWords tiles per span (else the fallback redoes whole spans).
-constexpr int kTileWords = 4;
+constexpr int kTileWords = 8;
 // static LDS of the path kernels (tile masks and redo states of a group)
 constexpr size_t kAdjStaticLds = 64 * kTileWords * 8 + 64 * 4 + 16;
 
