@@ -350,6 +350,15 @@ def accuracy(d, forms, n_long=3, n_rand=5, linear_scaling=True):
     return out
 
 
+def plain_launches(cfg):
+    """Launches per individual of the plain form: its forward, the gradient's
+    work-class kernels enabled for the shape (the individual's own class does
+    the work), the two binary64 passes and the gradient finalize."""
+    Cm, L = cfg.C_max, cfg.L_max
+    classes = sum([Cm >= 1, Cm > 4, Cm > 8, Cm > 16, Cm >= 1 and L >= 127])
+    return 1 + classes + 3
+
+
 def other_workload(gg, cid, steps, stream):
     """Fused fitness + gradient on another workload (full size, shipped
     tuning, graph replays): ms per step and node-evals/s, as context."""
@@ -474,7 +483,7 @@ def main():
             torch.cuda.synchronize()
         ms_plain = (time.perf_counter() - t0) * 1e3 / a.plain_steps
         out["plain"] = {"ms_per_step": ms_plain, "node_evals_per_s": work / (ms_plain * 1e-3),
-                        "launches_per_step": 5 * cfg.M}
+                        "launches_per_step": plain_launches(cfg) * cfg.M}
         out["speedup_vs_plain"] = ms_plain / ms_step
         forms["plain"] = (fp.cpu().numpy(), gp.cpu().numpy(), sp.cpu().numpy())
 

@@ -110,7 +110,7 @@ Layout layout_of(const Shape& s) {
   l.redo_span = take(M * kAdjChunks * l.adj_spans * sizeof(int32_t));
   l.rpool = take(kRedoPoolBytes);  // bad-tile masks of the binary64 fallback
   l.plist = take(M * kAdjChunks * sizeof(int32_t));  // plain form: per-individual entries
-  l.pcount = take(M * sizeof(int32_t));
+  l.pcount = take(M * kAdjClasses * sizeof(int32_t));  // per individual and work class
   l.pfb = take(M * 2 * kAdjChunks * kAdjParts * sizeof(int32_t));
   l.pfbc = take(M * 2 * sizeof(int32_t));
   l.pgpart = take(Cm * kPlainAdjSpans * sizeof(double));  // one individual's partials
@@ -435,8 +435,14 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
         constexpr int kFb = kAdjChunks * kAdjParts;
         int* fb = pfb + 2 * kFb * i;
         int* fbc = pfbc + 2 * i;
-        GG_TIMED("plain_adjoint", adj(kAdjPlain, 2, plist + e0, pcount + i, kAdjChunks, 1, P, ac.plain_span_rows,
-                                      pg, P, i, pspan, P, e0, fb, fbc, kFb, true));
+        // the individual's work class as in the fused form (the other four
+        // class launches find an empty list and return at once)
+        for (int cls = 0; cls < kAdjClasses; ++cls) {
+          if (!ac.on[cls]) continue;
+          const int K = cls >= 3 || ((ac.Kmask >> cls) & 1) ? 2 : 4;
+          GG_TIMED("plain_adjoint", adj(cls, K, plist + e0, pcount + size_t(i) * kAdjClasses + cls, kAdjChunks, 1,
+                                        P, ac.plain_span_rows, pg, P, i, pspan, P, e0, fb, fbc, kFb, true));
+        }
         GG_TIMED("plain_fallback", adj(kAdjFallback, 2, fb, fbc, kAdjChunks, 1, P, ac.plain_span_rows, pg, P, i,
                                        pspan, P, e0, nullptr, nullptr, 0, true));
         GG_TIMED("plain_fallback", adj(kAdjFallbackWide, 2, fb + kFb, fbc + 1, kAdjChunks, 1, P,

@@ -181,7 +181,8 @@ __global__ __launch_bounds__(kPartThreads) void k_adj_partition(
 }
 
 // Plain form: per individual i, its entries at plist[8i ..] and their number
-// pcount[i] (0 without gradient work); its two fallback counts pfb_count[2i],
+// in its work class, pcount[5i + class] (the other four counts 0, all five 0
+// without gradient work); its two fallback counts pfb_count[2i],
 // pfb_count[2i + 1] cleared; its per-entry fallback flags cleared.
 __global__ __launch_bounds__(256) void k_adj_plain_lists(const ProgMeta* __restrict__ meta,
                                                          const double* __restrict__ ab, int M,
@@ -190,13 +191,16 @@ __global__ __launch_bounds__(256) void k_adj_plain_lists(const ProgMeta* __restr
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   const ProgMeta pm = meta[i];
-  const int ne = adj_chunks(adj_class(pm, ab[size_t(i) * AB_WORDS + AB_S1]), pm.n_const);
-  const int nce = ne > 0 ? (pm.n_const + kChunk - 1) / kChunk : 0;  // one class: chunks of 32
+  const int c = adj_class(pm, ab[size_t(i) * AB_WORDS + AB_S1]);
+  const int ne = adj_chunks(c, pm.n_const);
   for (int k = 0; k < kMaxChunks; ++k) {
     plist[size_t(i) * kMaxChunks + k] = i * kMaxChunks + k;
     redo[size_t(i) * kMaxChunks + k] = 0;
   }
-  pcount[i] = nce;
+  // the work class the fused form gives the individual: its entries in that
+  // class's count, none in the others
+#pragma unroll
+  for (int q = 0; q < kAdjClasses; ++q) pcount[size_t(i) * kAdjClasses + q] = c == q ? ne : 0;
   pfb_count[2 * i] = 0;
   pfb_count[2 * i + 1] = 0;
 }
@@ -842,20 +846,20 @@ static hipError_t path_launch(const AdjParams& ap, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool ROLL>
+template <bool ROLL, bool SPLIT>
 static hipError_t class_launch(int cls, int K, const AdjParams& ap, hipStream_t s) {
   switch (cls) {
     case 0:
-      return K == 4 ? path_launch<4, kShallow, 4, ROLL, float, false>(ap, s)
-                    : path_launch<2, kShallow, 4, ROLL, float, false>(ap, s);
+      return K == 4 ? path_launch<4, kShallow, 4, ROLL, float, SPLIT>(ap, s)
+                    : path_launch<2, kShallow, 4, ROLL, float, SPLIT>(ap, s);
     case 1:
-      return K == 4 ? path_launch<4, kShallow, 8, ROLL, float, false>(ap, s)
-                    : path_launch<2, kShallow, 8, ROLL, float, false>(ap, s);
+      return K == 4 ? path_launch<4, kShallow, 8, ROLL, float, SPLIT>(ap, s)
+                    : path_launch<2, kShallow, 8, ROLL, float, SPLIT>(ap, s);
     case 2:
-      return K == 4 ? path_launch<4, kShallow, 16, ROLL, float, false>(ap, s)
-                    : path_launch<2, kShallow, 16, ROLL, float, false>(ap, s);
-    case 3: return path_launch<2, kShallow, kChunk, ROLL, float, false>(ap, s);
-    case 4: return path_launch<2, 8, kChunk, ROLL, float, false>(ap, s);
+      return K == 4 ? path_launch<4, kShallow, 16, ROLL, float, SPLIT>(ap, s)
+                    : path_launch<2, kShallow, 16, ROLL, float, SPLIT>(ap, s);
+    case 3: return path_launch<2, kShallow, kChunk, ROLL, float, SPLIT>(ap, s);
+    case 4: return path_launch<2, 8, kChunk, ROLL, float, SPLIT>(ap, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -894,11 +898,10 @@ hipError_t launch_adjoint_class(const AdjLaunch& L, hipStream_t s) {
     return roll ? path_launch<2, 8, kSub, true, double, false>(ap, s)
                 : path_launch<2, 8, kSub, false, double, false>(ap, s);
   }
-  if (L.cls == kAdjPlain) {  // plain form: any shallow or deep entry, waves share it
-    return roll ? path_launch<2, 8, kChunk, true, float, true>(ap, s)
-                : path_launch<2, 8, kChunk, false, float, true>(ap, s);
-  }
-  return roll ? class_launch<true>(L.cls, L.K, ap, s) : class_launch<false>(L.cls, L.K, ap, s);
+  // a class kernel; in the plain form (split) the block's waves share each entry
+  if (L.split)
+    return roll ? class_launch<true, true>(L.cls, L.K, ap, s) : class_launch<false, true>(L.cls, L.K, ap, s);
+  return roll ? class_launch<true, false>(L.cls, L.K, ap, s) : class_launch<false, false>(L.cls, L.K, ap, s);
 }
 
 // ------------------------------------------------------------ grad finalize

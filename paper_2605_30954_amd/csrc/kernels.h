@@ -82,12 +82,12 @@ int plain_blocks(const TileCfg& c, int64_t N);
 // Work classes of the path-forward-mode adjoint (see k_adjoint.hip): 0..3
 // shallow programs with at most 4, 8, 16, or more constants (chunks of 32),
 // 4 deep programs (more than four stack slots); kAdjFallback and
-// kAdjFallbackWide are the binary64 passes over the fallen-back entries (at
-// most 8 constants and 4 slots, or any), kAdjPlain the plain form's one class.
+// kAdjFallbackWide are the binary64 passes over the fallen-back entries'
+// parts of 8 constants (at most 4 stack slots, or more).  The plain form
+// runs the same class kernels, one individual per launch.
 constexpr int kAdjClasses = 5;
 constexpr int kAdjFallback = 5;
 constexpr int kAdjFallbackWide = 6;
-constexpr int kAdjPlain = 7;
 constexpr int kAdjChunks = 8;   // entries per individual at most (GPGOMEA_MAX_CONSTS / 32)
 constexpr int kAdjChunkNC = 32;  // constants per entry of the chunked classes
 constexpr int kAdjParts = 4;  // binary64 list items per entry (8 constants each)
