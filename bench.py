@@ -53,11 +53,13 @@ DERIV = {"add": {}, "sub": {}, "mul": {}, "sq": {"mul": 1}, "exp": {"mul": 1},
          "div": {"div": 1, "mul": 1}, "sin": {"cos": 1}, "cos": {"sin": 1},
          "sqrt": {"div": 1}, "log": {"div": 1}, "pow": {"log": 1, "mul": 2}}
 
-# sources the adjoint kernels are built from: a traffic summary is valid only
-# for the kernels, the workload and the launch shapes it was measured on
+# sources the adjoint kernels and their launch plan are built from: a traffic
+# summary is valid only for the kernels, the workload and the launch shapes it
+# was measured on
 ADJ_SOURCES = ["paper_2605_30954_amd/csrc/k_adjoint.hip", "paper_2605_30954_amd/csrc/interp.h",
                "paper_2605_30954_amd/csrc/devmath.h", "paper_2605_30954_amd/csrc/uop.h",
-               "paper_2605_30954_amd/csrc/kernels.h", "paper_2605_30954_amd/build.py"]
+               "paper_2605_30954_amd/csrc/kernels.h", "paper_2605_30954_amd/csrc/api.cpp",
+               "paper_2605_30954_amd/build.py"]
 ADJ_KERNELS = ("k_adj_partition", "k_adj_path")
 ADJ_PARTS = ("adjoint_partition", "adjoint_c4", "adjoint_c8", "adjoint_c16", "adjoint_c32",
              "adjoint_deep", "adjoint_fallback")

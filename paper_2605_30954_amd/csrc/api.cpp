@@ -1005,7 +1005,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
     // the path classes' tile R and group G, and which of classes 0-2 run two
     // rows per lane (K mask; only the classes the shape can populate vary)
     const int Rs_a[3] = {256, 512, 1024};
-    const int Gs_a[3] = {8, 16, 32};
+    const int Gs_a[4] = {8, 16, 32, 64};
     const int kmasks[4] = {0, 4, 6, 7};  // class 2 first: its register array is the largest
     Tuned best_a{-1, 0, 0};
     float best_a_ms = 1e30f;
