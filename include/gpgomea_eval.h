@@ -229,19 +229,30 @@ int gpgomea_encode(const int8_t* genes, const float* gene_consts, int32_t M, int
                    int32_t* bad_index);
 
 /* gpgomea_decode: rebuild heap-ordered genotypes of height `height` from
- * postfix programs (inverse of gpgomea_encode on the active nodes; every
- * other slot becomes -1 with constant 0).  E_PROGRAM if a program is malformed
- * or taller than the template. */
+ * postfix programs, the inverse of gpgomea_encode on the active nodes (Section
+ * 3.2, Fig. 1: a postfix program determines its tree, and the tree's root sits
+ * at heap slot 0 with operands in order).  Every other slot becomes -1 with
+ * constant 0.  genes[M][2^(height+1)-1] and gene_consts of the same shape are
+ * written by the call (host memory, caller-owned).  E_PROGRAM if a program is
+ * malformed or taller than the template; *bad_index (if not NULL) names it. */
 int gpgomea_decode(const int8_t* ops, const float* consts, int32_t M, int32_t L_max,
                    int32_t C_max, int32_t height, int8_t* genes, float* gene_consts,
                    int32_t* bad_index);
 
-/* gpgomea_validate: check host-resident programs the way the device does:
- * status_out[i] = 0 (valid) or 2 (unknown symbol, variable >= F, more than
- * C_max constants, stack underflow, not exactly one result).  Returns the
- * number of invalid programs (>= 0) or a negative error code. */
+/* gpgomea_validate: check host-resident postfix programs (Section 3.2's
+ * population arrays, END padded to L_max) the way the device does, and
+ * optionally against a template height.  A program is invalid (status 2) if
+ * it holds an unknown symbol, a variable >= F or more than C_max constants,
+ * underflows the stack, does not leave exactly one result, or, when
+ * max_height >= 0, its tree is taller than max_height (a terminal has height
+ * 0, an operator one more than its tallest operand: the depth of a template
+ * of that height, Section 3.1).  max_height = -1 skips the height check.
+ * status_out[M] (host, may be NULL) receives 0 or 2 per program; *first_bad
+ * (may be NULL) the index of the first invalid program or -1.  Returns the
+ * number of invalid programs (>= 0), or E_ARG / E_SHAPE before any program is
+ * read. */
 int gpgomea_validate(const int8_t* ops, int32_t M, int32_t L_max, int32_t C_max, int32_t F,
-                     int8_t* status_out);
+                     int32_t max_height, int8_t* status_out, int32_t* first_bad);
 
 /* ---- tuning -----------------------------------------------------------------
  * gpgomea_autotune: time the fused kernels over their launch parameters

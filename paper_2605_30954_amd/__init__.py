@@ -320,12 +320,14 @@ def decode(ops, consts, height):
     return g, gc
 
 
-def validate(ops, C_max, F):
+def validate(ops, C_max, F, max_height=-1, return_first_bad=False):
     o = _np(ops, np.int8)
     M, L = o.shape
     st = np.empty(M, np.int8)
-    check(lib.gpgomea_validate(o.ctypes.data, M, L, int(C_max), int(F), st.ctypes.data))
-    return st
+    first = ctypes.c_int32(-1)
+    check(lib.gpgomea_validate(o.ctypes.data, M, L, int(C_max), int(F), int(max_height),
+                               st.ctypes.data, ctypes.byref(first)))
+    return (st, first.value) if return_first_bad else st
 
 
 from .autograd import GPGOMEAFitness  # noqa: E402

@@ -38,7 +38,7 @@ SIGNATURES = {
                                               _p, _p, _p, _p]),
     "gpgomea_encode": (_c.c_int, [_p, _p, _i32, _i32, _i32, _p, _p, _i32, _p, _i32, _p, _p, _p]),
     "gpgomea_decode": (_c.c_int, [_p, _p, _i32, _i32, _i32, _i32, _p, _p, _p]),
-    "gpgomea_validate": (_c.c_int, [_p, _i32, _i32, _i32, _i32, _p]),
+    "gpgomea_validate": (_c.c_int, [_p, _i32, _i32, _i32, _i32, _i32, _p, _p]),
     "gpgomea_autotune": (_c.c_int, [_p, _i32, _i32, _p, _i32, _p, _i32, _i64, _i64, _p, _u32,
                                     _i32, _p, _sz, _c.c_char_p, _i32, _c.c_char_p, _i32, _p]),
     "gpgomea_load_tuning": (_c.c_int, [_c.c_char_p]),

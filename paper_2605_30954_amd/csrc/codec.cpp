@@ -189,19 +189,32 @@ extern "C" int gpgomea_decode(const int8_t* ops, const float* consts, int32_t M,
 }
 
 extern "C" int gpgomea_validate(const int8_t* ops, int32_t M, int32_t L_max, int32_t C_max,
-                                int32_t F, int8_t* status_out) {
-  if (!ops || !status_out) return fail(GPGOMEA_E_ARG, "NULL pointer");
+                                int32_t F, int32_t max_height, int8_t* status_out,
+                                int32_t* first_bad) {
+  if (first_bad) *first_bad = -1;
+  if (!ops) return fail(GPGOMEA_E_ARG, "NULL pointer");
   if (M < 0 || L_max < 1 || L_max > GPGOMEA_MAX_LEN || C_max < 0 || F < 1 ||
-      F > GPGOMEA_MAX_FEATURES)
+      F > GPGOMEA_MAX_FEATURES || max_height < -1)
     return fail(GPGOMEA_E_SHAPE, "bad shape");
-  std::vector<int> kids;
+  std::vector<int> kids, ht(size_t(L_max), 0);
   int bad = 0;
   std::string keep = last_error();
   for (int32_t i = 0; i < M; ++i) {
+    const int8_t* o = ops + size_t(i) * L_max;
     int nc = 0;
-    const int root = parse_one(ops + size_t(i) * L_max, L_max, F, C_max, kids, &nc);
-    status_out[i] = root < 0 ? 2 : 0;
-    bad += root < 0;
+    const int root = parse_one(o, L_max, F, C_max, kids, &nc);
+    bool ok = root >= 0;
+    if (ok && max_height >= 0) {
+      // operands precede their operator, so one forward pass gives every height
+      for (int t = 0; t <= root; ++t) {
+        const int a = kids[2 * size_t(t)], b = kids[2 * size_t(t) + 1];
+        ht[t] = a < 0 ? 0 : 1 + (b < 0 ? ht[a] : (ht[a] > ht[b] ? ht[a] : ht[b]));
+      }
+      ok = ht[root] <= max_height;
+    }
+    if (status_out) status_out[i] = ok ? 0 : 2;
+    if (!ok && first_bad && *first_bad < 0) *first_bad = i;
+    bad += !ok;
   }
   last_error() = keep;
   return bad;

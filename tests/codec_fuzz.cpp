@@ -65,7 +65,9 @@ int main() {
       }
       // (the encoder does not know F: a stray byte may name any variable)
       std::vector<int8_t> st(M);
-      if (gpgomea_validate(ops.data(), M, L_max, C_max, GPGOMEA_MAX_FEATURES, st.data()) < 0) {
+      int32_t first = 0;
+      if (gpgomea_validate(ops.data(), M, L_max, C_max, GPGOMEA_MAX_FEATURES, H, st.data(), &first) != 0 ||
+          first != -1) {
         std::printf("validate refused an encoded batch at case %d\n", it);
         return 1;
       }
@@ -78,7 +80,12 @@ int main() {
     // random bytes through validate
     std::vector<int8_t> rb(size_t(M) * L_max), st(M);
     for (auto& b : rb) b = int8_t(uni(0, 3) ? uni(-1, 80) : uni(-128, 127));
-    (void)gpgomea_validate(rb.data(), M, L_max, C_max, F, st.data());
+    int32_t first = 0;
+    const int nbad = gpgomea_validate(rb.data(), M, L_max, C_max, F, int32_t(uni(-1, 8)), st.data(), &first);
+    if (nbad < 0 || (nbad == 0) != (first == -1) || (first >= 0 && st[size_t(first)] != 2)) {
+      std::printf("validate counts disagree at case %d\n", it);
+      return 1;
+    }
     ++cases;
   }
   std::printf("ok %ld cases, %ld round trips\n", cases, trips);

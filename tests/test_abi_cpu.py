@@ -73,6 +73,23 @@ def test_exhaustive_height2_library_vs_oracle():
     assert (dg == og).all() and (dc.view(np.uint32) == oc.view(np.uint32)).all()
 
 
+def test_exhaustive_height2_validate_heights():
+    """validate's height check against the genotype: a program is taller than
+    h exactly when one of its active slots lies below depth h of the template
+    (Section 3.1's fixed template; depth from the heap index)."""
+    from oracle.tree import active_slots, depth_of
+    genes, gc = all_height2_genotypes()
+    ops, cs, ln, nc = gg.encode(genes, gc, 2, 7, 4)
+    depth = np.array([max(depth_of(s) for s in active_slots(g, 2)) for g in genes])
+    assert set(depth.tolist()) == {0, 1, 2}
+    for h in (-1, 0, 1, 2, 3):
+        st, first = gg.validate(ops, 4, 2, max_height=h, return_first_bad=True)
+        want = np.zeros(len(genes), np.int8) if h < 0 else np.where(depth > h, 2, 0).astype(np.int8)
+        assert (st == want).all()
+        bad = np.flatnonzero(want)
+        assert first == (int(bad[0]) if len(bad) else -1)
+
+
 @pytest.mark.parametrize("cid", sorted(CONFIGS))
 def test_workload_populations_library_vs_oracle(cid):
     cfg = get_config(cid)
@@ -117,6 +134,22 @@ def test_validate_statuses():
         ops[i, : len(p)] = p
     st = gg.validate(ops, 2, 2)
     assert st.tolist() == [0, 2, 2, 2, 2, 2, 2, 0]
+    # heights of the two valid programs: 1 and 1
+    st, first = gg.validate(ops, 2, 2, max_height=1, return_first_bad=True)
+    assert st.tolist() == [0, 2, 2, 2, 2, 2, 2, 0] and first == 1
+    st, first = gg.validate(ops, 2, 2, max_height=0, return_first_bad=True)
+    assert st.tolist() == [2] * 8 and first == 0
+    ok = ops[[0, 7]]
+    st, first = gg.validate(ok, 2, 2, max_height=0, return_first_bad=True)
+    assert st.tolist() == [2, 2] and first == 0
+    st, first = gg.validate(ok, 2, 2, max_height=1, return_first_bad=True)
+    assert st.tolist() == [0, 0] and first == -1
+    # NULL status array: only the count and the first index
+    f = ctypes.c_int32(7)
+    assert gg.lib.gpgomea_validate(ops.ctypes.data, 8, 8, 2, 2, -1, None, ctypes.byref(f)) == 6
+    assert f.value == 1
+    with pytest.raises(gg.LibraryError):
+        gg.validate(ops, 2, 2, max_height=-2)
 
 
 def test_host_side_argument_errors():
