@@ -138,8 +138,8 @@ def load_traffic(workload, tuning):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=5, help="workload number 1..5 (default 5)")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
@@ -387,6 +387,27 @@ def other_workload(gg, cid, steps, stream):
     return {"workload": f"cfg{cid}: {cfg.description}", "ms_per_step": ms, "node_evals_per_s": work / (ms * 1e-3)}
 
 
+def device_info(dev):
+    """Name, CU count and, where the driver's sysfs file is readable, the
+    current shader clock level of the GPU the step ran on."""
+    import glob
+    import torch
+    pr = torch.cuda.get_device_properties(dev)
+    info = {"name": pr.name, "arch": getattr(pr, "gcnArchName", None), "cus": pr.multi_processor_count,
+            "sclk": None}
+    bus = f"{pr.pci_domain_id:04x}:{pr.pci_bus_id:02x}:{pr.pci_device_id:02x}"
+    for path in glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"):
+        try:
+            if bus not in os.path.realpath(os.path.dirname(path)).lower():
+                continue
+            with open(path) as f:
+                cur = [ln.split(":", 1)[1].strip().rstrip("*").strip() for ln in f if ln.rstrip().endswith("*")]
+            info["sclk"] = cur[0] if cur else None
+        except (OSError, IndexError):
+            pass
+    return info
+
+
 def encode_upload(gg, genes, gc, hv, cfg, ops, cs, ops_d, cs_d, stream, work, ms_step, reps=10):
     """Genotype -> postfix on the host (the C codec) and the host-to-device copy
     of the encoded batch from pinned memory, timed apart from the device work
@@ -469,18 +490,21 @@ def main():
             step()
     torch.cuda.synchronize()
     # ---- timed region: fused fitness + adjoint, graph replays
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # (an event between consecutive steps on the step's stream gives each
+    # step's own time as well)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        e0.record(stream)
-        for _ in range(a.steps):
+        evs[0].record(stream)
+        for k in range(a.steps):
             fit, grad, st = step()
-        e1.record(stream)
+            evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = max(wall * 1e3 / a.steps, e0.elapsed_time(e1) / a.steps)
+    ms_step = max(wall * 1e3 / a.steps, evs[0].elapsed_time(evs[-1]) / a.steps)
     value = work / (ms_step * 1e-3)
+    per_step = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(a.steps)])
     fit_np, grad_np, st_np = fit.cpu().numpy(), grad.cpu().numpy(), st.cpu().numpy()
 
     out = {"metric": METRIC, "value": value, "unit": "node-evals/s", "n_gpus": 1,
@@ -492,7 +516,11 @@ def main():
                       "sum_active_tokens": int(lens.astype(np.int64).sum()),
                       "node_evals_per_step": work, "linear_scaling": True,
                       "form": "fused batched fitness + adjoint, one hipGraph launch per step",
-                      "tuning": tdesc}}
+                      "tuning": tdesc},
+           "step_ms": {"median": float(np.median(per_step)), "p10": float(np.percentile(per_step, 10)),
+                       "p90": float(np.percentile(per_step, 90)), "n": int(a.steps)},
+           "individual_evals_per_s": cfg.M / (ms_step * 1e-3),
+           "device": device_info(dev)}
 
     # ---- fused fitness only (same batch)
     with torch.cuda.stream(stream):
