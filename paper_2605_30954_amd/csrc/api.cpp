@@ -182,9 +182,9 @@ TileCfg plan_forward(const Shape& s, const Tuned* t) {
   }
   c.R = std::max(c.R, 64 * c.K);
   c.R = c.R / (64 * c.K) * (64 * c.K);
-  // at most 64 programs per group: the forward kernel keeps a group's
-  // metadata in a 64-entry LDS table
-  c.G = std::max(1, std::min({c.G, s.M, 64}));
+  // at most kFwdMaxG programs per group: the forward kernel keeps a group's
+  // metadata in an LDS table of that size
+  c.G = std::max(1, std::min({c.G, s.M, kFwdMaxG}));
   finish_spans(c, s.M, s.N, kMaxSpans);
   return c;
 }
@@ -496,8 +496,9 @@ int run_call(const Call& c) {
   plans_for(c.s, fc, ac);
   if (c.with_grad && !adjoint_plan_fits(c.s, ac))
     return fail(GPGOMEA_E_UNSUPPORTED, "no adjoint block fits LDS for F=%d", c.s.F);
-  if (fc.G > 64 || ac.G > 64)
-    return fail(GPGOMEA_E_UNSUPPORTED, "group of more than 64 programs (forward %d, adjoint %d)", fc.G, ac.G);
+  if (fc.G > kFwdMaxG || ac.G > 64)
+    return fail(GPGOMEA_E_UNSUPPORTED, "group too large (forward %d of at most %d, adjoint %d of at most 64)",
+                fc.G, kFwdMaxG, ac.G);
   const bool graph =
       !(c.s.flags & (GPGOMEA_NO_GRAPH | GPGOMEA_PLAIN)) && c.stream != nullptr && !g_prof;
   if (!graph) return enqueue_fused(c, fc, ac);
@@ -667,7 +668,8 @@ extern "C" int gpgomea_eval_batch_noalloc(const int8_t* ops, int32_t M, int32_t 
   TileCfg fc;
   AdjPlan ac;
   plans_for(s, fc, ac);
-  if (fc.G > 64) return fail(GPGOMEA_E_UNSUPPORTED, "group of more than 64 programs (forward %d)", fc.G);
+  if (fc.G > kFwdMaxG)
+    return fail(GPGOMEA_E_UNSUPPORTED, "group of more than %d programs (forward %d)", kFwdMaxG, fc.G);
   // direct launches only: no graph instantiation, no timing events
   t_no_alloc = true;
   rc = enqueue_fused(c, fc, ac);
@@ -966,7 +968,7 @@ extern "C" int gpgomea_autotune(const int8_t* ops, int32_t M, int32_t L_max, con
   // forward: rows per lane K, rows per LDS tile R, individuals per group G
   const int Ks_f[2] = {8, 4};
   const int Rs_f[4] = {256, 512, 1024, 2048};
-  const int Gs_f[3] = {16, 32, 64};
+  const int Gs_f[4] = {16, 32, 64, 128};
   const int lds = lds_limit_bytes();
   Tuned best_f{0, 0, 0};
   float best_f_ms = 1e30f;

@@ -127,9 +127,10 @@ __global__ __launch_bounds__(W * 64) void k_fused_fwd(FwdParams p) {
     if (!any) return;
   }
   __shared__ int queue;
-  // status (0 evaluate, else skip) and mu of the group's individuals (G <= 64),
-  // read with the queue claim: one LDS round trip per individual, no global load
-  __shared__ uint2 gmeta[64];
+  // status (0 evaluate, else skip) and mu of the group's individuals
+  // (G <= kFwdMaxG), read with the queue claim: one LDS round trip per
+  // individual, no global load
+  __shared__ uint2 gmeta[kFwdMaxG];
   for (int j = threadIdx.x; j < Gn * 4; j += blockDim.x) accs[j] = 0.0;
   for (int j = threadIdx.x; j < Gn; j += blockDim.x) {
     const ProgMeta& m = p.meta[ind0 + j];

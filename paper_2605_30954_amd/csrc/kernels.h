@@ -175,6 +175,10 @@ int lds_limit_bytes();
 int measure_op_costs(double* out, int n, int iters, hipStream_t s, float* scratch);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t s);
 
+// Programs per group of the forward kernel (its LDS table of the group's
+// status and shift holds this many).
+constexpr int kFwdMaxG = 128;
+
 inline size_t forward_lds_bytes(int F, int R, int G) {
   return size_t(F) * R * 4 + size_t(R) * 8 + size_t(G) * 4 * 8 + 16;
 }

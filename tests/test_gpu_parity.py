@@ -119,3 +119,32 @@ def test_plain_and_fused_agree_and_are_deterministic():
     fin = np.isfinite(f1)
     np.testing.assert_allclose(f4[fin], f1[fin], rtol=1e-9, atol=1e-12)
     assert np.array_equal(np.isfinite(f4), fin)
+
+
+def test_forward_group_sizes_agree(tmp_path):
+    """Groups of 16, 64 and 128 programs (the forward's largest) with a ragged
+    last group: the oracle's gate for the largest, and bitwise the same
+    fitness for all three (a program's sums do not depend on its group)."""
+    cfg = get_config(2)
+    M, N = 300, 5000
+    d = make_inputs(cfg, M, N, salt=21)
+    ops, cs, X, y = to_device(d)
+    lcls = int(np.floor(np.log2(cfg.L_max + 1)))
+    outs = {}
+    for G in (16, 64, 128):
+        path = str(tmp_path / f"fwd_{G}.json")
+        with open(path, "w") as fh:
+            fh.write('{"entries": [\n  {"table": "fwd", "fp64": 0, "Lcls": %d, "F": %d, "Ncls": %d, '
+                     '"Mcls": %d, "grad": 0, "K": 8, "R": 512, "G": %d}\n]}\n'
+                     % (lcls, cfg.F, int(np.log2(N)), int(np.log2(M)), G))
+        assert gg.load_tuning(path) == 1
+        log(f"[case] forward group size {G}, cfg2 M={M} N={N}")
+        fit, st = gg.eval_batch(ops, cs, X, y, return_status=True)
+        outs[G] = (fit.cpu().numpy(), st.cpu().numpy())
+    for G in (16, 64):
+        assert np.array_equal(outs[G][1], outs[128][1])
+        assert np.array_equal(outs[G][0].view(np.uint64), outs[128][0].view(np.uint64)), G
+    idx = list(range(M))
+    vy = float(np.var(d["y"].astype(np.float64)))
+    gate_fitness(outs[128][0], outs[128][1], oracle_scores(d, idx), oracle_flags(d, idx), vy, "f32",
+                 "cfg2 forward groups of 128")
