@@ -30,11 +30,12 @@
 //
 // Binary64 fallback.  The chain-rule products are binary32; a product taken
 // from the leaves up can leave the binary32 range while the true partial does
-// not (or the true partial itself can exceed it).  A (entry, span) whose sums
-// are not finite is recomputed by the same kernel in binary64 chain-rule
-// arithmetic (node values stay binary32, identical to the forward pass), in
-// one of two fallback classes: at most 8 constants and 4 stack slots (2 rows
-// per lane), or any entry (1 row per lane, 32 constants, 8 slots).
+// not (or the true partial itself can exceed it).  The row tiles of an entry
+// whose sums are not finite are recomputed by the same kernel in binary64
+// chain-rule arithmetic (node values stay binary32, identical to the forward
+// pass), in parts of 8 constants, by one of two fallback classes: 4 stack
+// slots (4 rows per lane; 2 in the one-program form), or 8 slots (2 rows per
+// lane).
 //
 // Every (entry, span) partial has exactly one writer (two in order for a
 // fallen-back span), so results are bitwise repeatable for a fixed plan.
@@ -889,8 +890,8 @@ hipError_t launch_adjoint_class(const AdjLaunch& L, hipStream_t s) {
   if (L.cls == kAdjFallback) {  // binary64 chain rule: parts of 8 constants, 4 slots
     if (L.split) return roll ? path_launch<2, kShallow, kSub, true, double, true>(ap, s)
                              : path_launch<2, kShallow, kSub, false, double, true>(ap, s);
-    return roll ? path_launch<2, kShallow, kSub, true, double, false>(ap, s)
-                : path_launch<2, kShallow, kSub, false, double, false>(ap, s);
+    return roll ? path_launch<4, kShallow, kSub, true, double, false>(ap, s)
+                : path_launch<4, kShallow, kSub, false, double, false>(ap, s);
   }
   if (L.cls == kAdjFallbackWide) {  // binary64 chain rule: parts of 8 constants, 8 slots
     if (L.split) return roll ? path_launch<2, 8, kSub, true, double, true>(ap, s)
