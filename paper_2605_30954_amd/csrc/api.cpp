@@ -154,7 +154,21 @@ void finish_spans(TileCfg& c, int M, int64_t N, int max_spans) {
   c.n_spans = int((tiles + c.tiles_per_span - 1) / c.tiles_per_span);
 }
 
-int forward_lds_cap() { return std::min(lds_limit_bytes(), 64 * 1024); }
+// untuned forward tiles: at most 40 KB of LDS, so that four blocks (four waves
+// per SIMD, what the eight-rows-per-lane forward is compiled for) share a CU
+int forward_lds_cap() { return std::min(lds_limit_bytes(), 40 * 1024); }
+
+// Row tile of the one-program-per-launch form: the largest of 2048, 1024, ...
+// rows (a multiple of its batch) whose LDS stays within 64 KB.  It does not
+// follow the fused kernel's tuned tile, which is sized for four blocks per CU.
+int plain_tile_rows(const Shape& s, int K) {
+  const int BR = 64 * K;
+  int R = 2048;
+  while (R > BR && size_t(s.F) * R * 4 + size_t(R) * 8 > size_t(64 * 1024)) R /= 2;
+  const int64_t Nr = (s.N + BR - 1) / BR * BR;
+  if (Nr < R) R = int(Nr);
+  return std::max(R, BR);
+}
 
 TileCfg plan_forward(const Shape& s, const Tuned* t) {
   TileCfg c;
@@ -417,8 +431,10 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     unsigned* ticket = reinterpret_cast<unsigned*>(ws + l.ticket);
     double* pp = reinterpret_cast<double*>(ws + l.plain_part);
     GG_HIP(launch_fill_u32(ticket, 1, 0u, c.stream));
+    TileCfg pc = fc;
+    pc.R = plain_tile_rows(c.s, fc.K);
     for (int i = 0; i < M; ++i)
-      GG_TIMED("plain_forward", launch_plain_forward(fp64, fc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
+      GG_TIMED("plain_forward", launch_plain_forward(fp64, pc, i, uops, l.U_stride, meta, d, stats, pp, ticket,
                                                      c.s.flags, c.fitness, c.aux, c.status, ab, c.stream));
     if (grad_work) {
       int* plist = reinterpret_cast<int*>(ws + l.plist);
