@@ -615,8 +615,22 @@ __device__ inline bool span_flagged(const AdjParams& p, int e, int span) {
 // individual per launch): all W waves share each entry, wave w taking batches
 // w, w+W, ... with its own copy of the accumulators, summed in wave order at
 // the end (bitwise repeatable).
+// Waves per SIMD a class kernel is compiled for.  The binary32 classes of at
+// most 8 constants at four rows per lane ask for four (at most 128 VGPRs, some
+// values then kept in scratch), which pays where four blocks fit a CU's LDS
+// (under 40 KB each: 512-row tiles of 9 or 10 features, 1024-row tiles of 5).
+// Measured on MI355X at full size: the <= 4 and <= 8 classes 12% and 5%
+// faster than at three waves (140-160 VGPRs) on the large-template workload,
+// the whole gradient 7-12% faster on the height-5 and mixed-height ones; with
+// 1024-row tiles of 9 features only three blocks fit and the hint costs 2-4%.
+// The larger classes stay at two waves: their register array T does not fit
+// 128 VGPRs.
+template <int K, int NC, typename C>
+constexpr int adj_min_waves() {
+  return (sizeof(C) == 4 && K == 4 && NC <= 8) ? 4 : GG_ADJ_MINW;
+}
 template <int K, int D, int W, int NC, bool ROLL, typename C, bool SPLIT>
-__global__ __launch_bounds__(W * 64, GG_ADJ_MINW) void k_adj_path(AdjParams p) {
+__global__ __launch_bounds__(W * 64, (adj_min_waves<K, NC, C>())) void k_adj_path(AdjParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr bool F64 = sizeof(C) == 8;
   constexpr bool SUB = F64;  // the binary64 pass works on parts of 8 constants
