@@ -615,19 +615,23 @@ __device__ inline bool span_flagged(const AdjParams& p, int e, int span) {
 // individual per launch): all W waves share each entry, wave w taking batches
 // w, w+W, ... with its own copy of the accumulators, summed in wave order at
 // the end (bitwise repeatable).
-// Waves per SIMD a class kernel is compiled for.  The binary32 classes of at
-// most 8 constants at four rows per lane ask for four (at most 128 VGPRs, some
-// values then kept in scratch), which pays where four blocks fit a CU's LDS
-// (under 40 KB each: 512-row tiles of 9 or 10 features, 1024-row tiles of 5).
-// Measured on MI355X at full size: the <= 4 and <= 8 classes 12% and 5%
-// faster than at three waves (140-160 VGPRs) on the large-template workload,
-// the whole gradient 7-12% faster on the height-5 and mixed-height ones; with
-// 1024-row tiles of 9 features only three blocks fit and the hint costs 2-4%.
-// The larger classes stay at two waves: their register array T does not fit
-// 128 VGPRs.
+// Waves per SIMD a class kernel is compiled for, trading registers for
+// occupancy where it measured faster on MI355X (at full size, 512-row tiles):
+// - the binary32 classes of at most 8 constants at four rows per lane ask for
+//   four (128 VGPRs, some values then kept in scratch); four blocks fit a
+//   CU's LDS when a block needs under 40 KB (512-row tiles of 9 or 10
+//   features, 1024-row tiles of 5).  The <= 4 and <= 8 classes ran 12% and
+//   5% faster than at three waves on the large-template workload, 7-12% on
+//   the height-5 and mixed-height ones; with 1024-row tiles of 9 features
+//   only three blocks fit and the hint costs 2-4%;
+// - the binary32 classes of 16 and 32 constants ask for three (168 VGPRs
+//   instead of 195-200, the register array T partly in scratch): 634 -> 511
+//   ms and 199 -> 191 ms on the large-template workload;
+// - the binary64 redo keeps what the compiler picks (two or three waves).
 template <int K, int NC, typename C>
 constexpr int adj_min_waves() {
-  return (sizeof(C) == 4 && K == 4 && NC <= 8) ? 4 : GG_ADJ_MINW;
+  if constexpr (sizeof(C) != 4) return GG_ADJ_MINW;
+  return (K == 4 && NC <= 8) ? 4 : NC >= 16 ? 3 : GG_ADJ_MINW;
 }
 template <int K, int D, int W, int NC, bool ROLL, typename C, bool SPLIT>
 __global__ __launch_bounds__(W * 64, (adj_min_waves<K, NC, C>())) void k_adj_path(AdjParams p) {
