@@ -44,9 +44,6 @@
 #include "interp.h"
 #include "kernels.h"
 
-#ifndef GG_ADJ_MINW
-#define GG_ADJ_MINW 1
-#endif
 
 namespace gg {
 
@@ -616,22 +613,22 @@ __device__ inline bool span_flagged(const AdjParams& p, int e, int span) {
 // w, w+W, ... with its own copy of the accumulators, summed in wave order at
 // the end (bitwise repeatable).
 // Waves per SIMD a class kernel is compiled for, trading registers for
-// occupancy where it measured faster on MI355X (at full size, 512-row tiles):
-// - the binary32 classes of at most 8 constants at four rows per lane ask for
-//   four (128 VGPRs, some values then kept in scratch); four blocks fit a
-//   CU's LDS when a block needs under 40 KB (512-row tiles of 9 or 10
-//   features, 1024-row tiles of 5).  The <= 4 and <= 8 classes ran 12% and
-//   5% faster than at three waves on the large-template workload, 7-12% on
-//   the height-5 and mixed-height ones; with 1024-row tiles of 9 features
-//   only three blocks fit and the hint costs 2-4%;
-// - the binary32 classes of 16 and 32 constants ask for three (168 VGPRs
-//   instead of 195-200, the register array T partly in scratch): 634 -> 511
-//   ms and 199 -> 191 ms on the large-template workload;
-// - the binary64 redo keeps what the compiler picks (two or three waves).
+// occupancy where it measured faster on MI355X (full size, 512-row tiles, so
+// that a block needs under 40 KB of LDS and four share a CU):
+// - the binary32 classes of at most 16 constants ask for four (128 VGPRs,
+//   some values and part of the register array T then kept in scratch): on
+//   the large-template workload the <= 4 and <= 8 classes ran 12% and 5%
+//   faster than at three waves, the <= 16 class 634 -> 513 -> 488 ms from
+//   two to three to four waves; 7-12% on the height-5 and mixed-height
+//   workloads.  With 1024-row tiles of 9 features only three blocks fit the
+//   LDS and the request costs 2-4%;
+// - the chunks of 32 constants ask for three (168 VGPRs): 199 -> 191 ms;
+// - the binary64 redo asks for three (168 VGPRs instead of 224): about 20%
+//   faster.
 template <int K, int NC, typename C>
 constexpr int adj_min_waves() {
-  if constexpr (sizeof(C) != 4) return GG_ADJ_MINW;
-  return (K == 4 && NC <= 8) ? 4 : NC >= 16 ? 3 : GG_ADJ_MINW;
+  if constexpr (sizeof(C) != 4) return 3;
+  return NC <= 16 ? 4 : 3;
 }
 template <int K, int D, int W, int NC, bool ROLL, typename C, bool SPLIT>
 __global__ __launch_bounds__(W * 64, (adj_min_waves<K, NC, C>())) void k_adj_path(AdjParams p) {
