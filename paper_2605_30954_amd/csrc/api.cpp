@@ -154,13 +154,13 @@ void finish_spans(TileCfg& c, int M, int64_t N, int max_spans) {
   c.n_spans = int((tiles + c.tiles_per_span - 1) / c.tiles_per_span);
 }
 
-// untuned forward tiles: at most 40 KB of LDS, so that four blocks (four waves
+// untuned forward tiles: at most 31 KB of LDS, so that five blocks (five waves
 // per SIMD, what the eight-rows-per-lane forward is compiled for) share a CU
-int forward_lds_cap() { return std::min(lds_limit_bytes(), 40 * 1024); }
+int forward_lds_cap() { return std::min(lds_limit_bytes(), 31 * 1024); }
 
 // Row tile of the one-program-per-launch form: the largest of 2048, 1024, ...
 // rows (a multiple of its batch) whose LDS stays within 64 KB.  It does not
-// follow the fused kernel's tuned tile, which is sized for four blocks per CU.
+// follow the fused kernel's tuned tile, which is sized for five blocks per CU.
 int plain_tile_rows(const Shape& s, int K) {
   const int BR = 64 * K;
   int R = 2048;

@@ -104,15 +104,16 @@ __device__ inline bool in_pass(int pass, int slots) {
   return pass == PASS_ALL || (pass == PASS_SHALLOW ? slots <= kShallowSlots : slots > kShallowSlots);
 }
 
-// The binary32 forward at eight rows per lane is compiled for four waves per
-// SIMD (at most 128 VGPRs: the fourth register-stack slot then lives in
-// scratch memory, which only programs needing four slots touch): with a row
-// tile of at most 40 KB of LDS, four blocks of four waves share a CU.
-// Measured on MI355X, 9-15% faster than three waves at 140 VGPRs on the
-// workloads of 5e5 rows and more.
+// The binary32 forward at eight rows per lane is compiled for five waves per
+// SIMD (at most 96 VGPRs; part of the register stack then lives in scratch
+// memory, touched only by programs that need those slots): with a row tile of
+// at most 32 KB of LDS, five blocks of four waves share a CU.  Measured on
+// MI355X at full size on the large-template workload: 608, 539, 514 and
+// 557 ms at three, four, five and six waves per SIMD; five waves were also
+// 2-6% faster than four on the other workloads.
 template <typename T, int K>
 constexpr int fwd_min_waves() {
-  return (sizeof(T) == 4 && K == 8) ? 4 : 1;
+  return (sizeof(T) == 4 && K == 8) ? 5 : 1;
 }
 template <typename T, int K, int D, int W, bool SSE, bool ROLL, int PASS>
 __global__ __launch_bounds__(W * 64, (fwd_min_waves<T, K>())) void k_fused_fwd(FwdParams p) {
