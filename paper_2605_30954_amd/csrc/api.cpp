@@ -483,7 +483,11 @@ int enqueue_fused(const Call& c, const TileCfg& fc, const AdjPlan& ac) {
     for (int cls = 0; cls < kAdjClasses; ++cls) {
       if (!ac.on[cls]) continue;
       const int K = cls >= 3 || ((ac.Kmask >> cls) & 1) ? 2 : 4;
-      GG_TIMED(kClassName[cls], adj(cls, K, lists + size_t(cls) * l.lstride, counts + cls, ac.G, ac.n_groups[cls],
+      // the chunked classes (32 constants per entry) work in groups of at
+      // most 32, so that their blocks' binary64 accumulators leave room for
+      // four blocks per CU (the waves they are compiled for)
+      const int G = cls >= 3 ? std::min(ac.G, 32) : ac.G;
+      GG_TIMED(kClassName[cls], adj(cls, K, lists + size_t(cls) * l.lstride, counts + cls, G, ac.n_groups[cls],
                                     S, ac.span_rows, gpart, gs, 0, redo_span, gs, 0, fbl, fbc, l.fbstride, false));
     }
     GG_TIMED("adjoint_fallback", adj(kAdjFallback, 2, fbl, fbc, ac.fb_G, ac.fb_groups, S, ac.span_rows, gpart, gs,

@@ -615,20 +615,22 @@ __device__ inline bool span_flagged(const AdjParams& p, int e, int span) {
 // Waves per SIMD a class kernel is compiled for, trading registers for
 // occupancy where it measured faster on MI355X (full size, 512-row tiles, so
 // that a block needs under 40 KB of LDS and four share a CU):
-// - the binary32 classes of at most 16 constants ask for four (128 VGPRs,
-//   some values and part of the register array T then kept in scratch): on
-//   the large-template workload the <= 4 and <= 8 classes ran 12% and 5%
-//   faster than at three waves, the <= 16 class 634 -> 513 -> 488 ms from
-//   two to three to four waves; 7-12% on the height-5 and mixed-height
-//   workloads.  With 1024-row tiles of 9 features only three blocks fit the
-//   LDS and the request costs 2-4%;
-// - the chunks of 32 constants ask for three (168 VGPRs): 199 -> 191 ms;
+// - the binary32 classes ask for four (128 VGPRs, some values and part of the
+//   register array T then kept in scratch): on the large-template workload
+//   the <= 4 and <= 8 classes ran 12% and 5% faster than at three waves, the
+//   <= 16 class 634 -> 513 -> 486 ms from two to three to four waves, the
+//   chunks of 32 (in groups of at most 32, whose blocks then fit four to a
+//   CU) 199 -> 191 -> 134 ms from two to three to four; 7-12% on the
+//   height-5 and mixed-height workloads.  With 1024-row tiles of 9 features
+//   only three blocks fit the LDS and the request costs 2-4%;
+// - the <= 8 class at four rows per lane asks for five (96 VGPRs): 2% faster
+//   than at four;
 // - the binary64 redo asks for three (168 VGPRs instead of 224): about 20%
-//   faster.
+//   faster than at two.
 template <int K, int NC, typename C>
 constexpr int adj_min_waves() {
   if constexpr (sizeof(C) != 4) return 3;
-  return NC <= 16 ? 4 : 3;
+  return (K == 4 && NC == 8) ? 5 : 4;
 }
 template <int K, int D, int W, int NC, bool ROLL, typename C, bool SPLIT>
 __global__ __launch_bounds__(W * 64, (adj_min_waves<K, NC, C>())) void k_adj_path(AdjParams p) {
